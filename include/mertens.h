@@ -1,0 +1,159 @@
+/*
+ * mertens.h -- C ABI of the MI355X (gfx950) exact Mertens-function library.
+ *
+ * Computes M(n) = sum_{y<=n} mu(y) exactly for 0 <= n < 2^64 by the blocked
+ * method of Kuznetsov, "Computing the Mertens function on a GPU"
+ * (arXiv:1108.0135), Section 2 (identity and blocking) and Section 3
+ * (segmented Moebius block sieve, per-block contribution update, finalize).
+ * Every step of the computation runs in HIP kernels on one GPU; this header
+ * uses plain C types only (no HIP or PyTorch types in any signature).
+ *
+ * Conventions shared by every entry point:
+ *   - Return value 0 on success, or a negative errno-style code:
+ *       MERTENS_EINVAL   bad argument (null pointer with count > 0, bad block
+ *                        size, u too small for some n, ...)
+ *       MERTENS_ENOMEM   device or host allocation failed; nothing written
+ *       MERTENS_ENODEV   no usable GPU, or the context is not initialised
+ *       MERTENS_ERANGE   index out of range (byproducts)
+ *       MERTENS_EIO      a HIP runtime call or kernel launch failed
+ *       MERTENS_EAGAIN   no free slot (serving)
+ *       MERTENS_EINPROGRESS  result not ready yet (serving)
+ *     mertens_strerror() turns a code into text; mertens_last_error() returns
+ *     the text of the last failure with detail (file/line of the HIP call).
+ *   - Pointers are HOST pointers unless stated otherwise; the caller owns
+ *     them and the library never keeps them past the call.
+ *   - No call is thread-safe: one context per process, one owner thread.
+ *   - Results are exact integers (no tolerance); identical bits whatever the
+ *     block size, u, tiling or batch composition.
+ */
+#ifndef MERTENS_H
+#define MERTENS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MERTENS_EINVAL (-22)
+#define MERTENS_ENOMEM (-12)
+#define MERTENS_ENODEV (-19)
+#define MERTENS_ERANGE (-34)
+#define MERTENS_EIO (-5)
+#define MERTENS_EAGAIN (-11)
+#define MERTENS_EINPROGRESS (-115)
+
+/*
+ * mertens_init -- create (or re-create) the process-wide context on the
+ * current HIP device.
+ *   u      sieve limit used to split each query (Section 2: an array of
+ *          floor(n/u) entries A[x] = M(floor(n/x)) is built while M(y) is
+ *          sieved for y < u).  0 = automatic: about (sum of the batch's n)^(2/3).
+ *          A query n uses L = max(1, floor(n/u)) entries; L must stay below
+ *          2^31 (else mertens_query returns MERTENS_EINVAL).
+ *   block  y-block length of the sieve sweep (Section 3: y is processed in
+ *          blocks, in increasing order).  0 = automatic (2^30, or less when
+ *          the sweep is shorter).  Otherwise a multiple of 2^16 in
+ *          [2^16, 2^31].
+ * Returns 0, MERTENS_EINVAL (bad block), MERTENS_ENODEV, MERTENS_ENOMEM.
+ * Calling it again frees the previous context first.
+ */
+int mertens_init(uint64_t u, uint64_t block);
+
+/*
+ * mertens_query -- synchronous exact M(n[i]) for i < count.
+ *   n     host array of count arguments (any order, duplicates allowed,
+ *         0 <= n < 2^64; M(0) = 0 by convention, the empty sum).
+ *   out   host array of count int64 results, written only on success.
+ * All arguments of one call share one sieve sweep (Section 2: one sieve
+ * serves several close values of n), each with its own A array.  The A
+ * arrays stay on the device until the next query for mertens_byproducts().
+ * Returns 0, MERTENS_EINVAL, MERTENS_ENOMEM, MERTENS_ENODEV, MERTENS_EIO.
+ * count == 0 returns 0 and touches nothing.
+ */
+int mertens_query(const uint64_t *n, size_t count, int64_t *out);
+
+/*
+ * mertens_byproducts -- the other entries of query i's array from the last
+ * successful mertens_query (Section 1: one evaluation at n yields every
+ * M(floor(n/c)); the array holds them for c <= L = max(1, floor(n/u))).
+ *   i     index into the last query's n[] array
+ *   buf   host array of cap entries; buf[c-1] = M(floor(n_i/c)) for
+ *         c = 1 .. min(L, cap)
+ *   len   receives L (may be NULL)
+ * Returns 0, MERTENS_ERANGE (i >= last count), MERTENS_EINVAL (buf NULL with
+ * cap > 0), MERTENS_ENODEV, MERTENS_EIO.
+ */
+int mertens_byproducts(size_t i, int64_t *buf, size_t cap, size_t *len);
+
+/*
+ * mertens_set_stream -- run all further device work on the given HIP stream
+ * (a hipStream_t passed as void*; NULL = the library's own stream).  The
+ * caller keeps ownership and must keep it alive while the context uses it.
+ * Returns 0 or MERTENS_ENODEV.
+ */
+int mertens_set_stream(void *hip_stream);
+
+/*
+ * mertens_set_param -- tuning knobs (results never depend on them).
+ *   "beta"        split of the per-x sum between the run-length part over
+ *                 y <= Y and the explicit k part (K = floor(beta*sqrt(m))),
+ *                 in (0, 1]; default 0.5
+ *   "ychunk"      y per work item of the run-length part, multiple of 64
+ *   "kchunk"      k per work item of the explicit k part
+ *   "waves_per_cu" persistent update grid size per compute unit
+ * Returns 0 or MERTENS_EINVAL (unknown key or value out of range).
+ */
+int mertens_set_param(const char *key, double value);
+
+/*
+ * mertens_stats -- counters of the last mertens_query, for benchmarking.
+ * Writes up to cap doubles into vals in this order (returns how many):
+ *   0 sieved y (Ymax+1)   1 blocks         2 u used        3 sum of L
+ *   4 run-length pairs    5 explicit k pairs (pairs = (x, y) visits)
+ *   6 ms sieve kernels    7 ms scan+fixup  8 ms update prep  9 ms update
+ *  10 ms finalize         11 ms total device time          12 update launches
+ *  13 sieve launches
+ * Kernel times are HIP-event intervals on the library's stream.
+ */
+int mertens_stats(double *vals, int cap);
+
+/* mertens_shutdown -- free the context and every device buffer. */
+void mertens_shutdown(void);
+
+/* mertens_strerror -- static text for a return code. */
+const char *mertens_strerror(int code);
+
+/* mertens_last_error -- detail text of the last failure in this process. */
+const char *mertens_last_error(void);
+
+/*
+ * Diagnostics used by the test suite.
+ *
+ * mertens_debug_div -- exact floor(n[i] / d[i]) for d[i] in [1, 2^32) by the
+ * Granlund-Montgomery multiply-high method ("Division by invariant integers
+ * using multiplication", PLDI 1994, Fig. 4.1), the replacement for 64-bit
+ * hardware division that Section 3 asks for.  on_device = 0 runs the host
+ * build of the same routine (no GPU needed), 1 runs it in a kernel.
+ * Returns 0, MERTENS_EINVAL (d == 0 or d >= 2^32), MERTENS_ENODEV, MERTENS_EIO.
+ */
+int mertens_debug_div(const uint64_t *n, const uint64_t *d, size_t count,
+                      uint64_t *q, int on_device);
+
+/*
+ * mertens_debug_mu -- mu(y) for y in [y1, y1 + count) from the device sieve
+ * (Section 3, the 8-bit log-prime sieve with the corrected log rule) into
+ * the host array mu (int8), and, if mert != NULL, the window partial sums
+ * mert[i] = sum_{z=y1}^{y1+i} mu(z) read back through the device prefix
+ * scan (for y1 = 0 these are M(i)).  y1 + count <= 2^63, count <= 2^31.
+ * Uses a sweep of its own; does not disturb the last query's byproducts.
+ * Returns 0, MERTENS_EINVAL, MERTENS_ENOMEM, MERTENS_ENODEV, MERTENS_EIO.
+ */
+int mertens_debug_mu(uint64_t y1, size_t count, int8_t *mu, int64_t *mert);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MERTENS_H */

@@ -1,0 +1,96 @@
+// Internal declarations shared by the kernel file and the host runtime of
+// the gfx950 Mertens library.  Not part of the public ABI (include/mertens.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrt {
+
+// ---------------------------------------------------------------- constants
+// Sieve segment: one byte per y in LDS, processed by one workgroup.
+constexpr uint32_t SEG = 1u << 16;
+constexpr uint32_t SEG_WORDS = SEG / 64;     // 64-y mask words per segment
+constexpr int SIEVE_THREADS = 512;           // 8 waves, 2 mask words per thread
+// Pre-sieved pattern: log sums of 2,3,5,7,11,13 and square flags of 4 and 9
+// repeat with period lcm(2,3,5,7,11,13,4,9) = 180180.
+constexpr uint32_t PAT = 180180;
+constexpr uint32_t PAT_WORDS = (PAT + SEG) / 4 + 16;
+// Sieving primes below this bound are walked by a whole wavefront (lane i
+// takes the i-th multiple); larger ones by one lane each.
+constexpr uint32_t SMALL_P = 1024;
+// First index of the prime table that is sieved (table starts at 5; the
+// pattern covers 5, 7, 11, 13, so sieving starts at 17 = index 4).
+constexpr uint32_t FIRST_SIEVED = 4;
+constexpr int TILE = 64;                     // x per tile = one wavefront
+constexpr int UPD_THREADS = 256;             // 4 independent waves per workgroup
+
+// ---------------------------------------------------------------- arguments
+// One y-block [y1, y2] of the sweep; y1 is a multiple of SEG.
+struct BlockArgs {
+    uint64_t y1, y2;
+    uint32_t nseg;
+    uint32_t n_small;   // primes with index in [FIRST_SIEVED, n_small) are < SMALL_P
+    uint32_t n_sieve;   // primes with index < n_sieve are sieved (all p <= Psieve)
+    uint32_t n_sq;      // primes with index < n_sq have p^2 <= y2
+    uint32_t pat_off;   // y1 mod PAT
+    const uint32_t *primes;   // primes >= 5, ascending
+    const uint8_t *logp;      // ceil(log2 p) | 1
+    uint32_t *res;            // y1 mod p      (per block)
+    uint64_t *res2;           // y1 mod p^2    (per block)
+    const uint32_t *pat32;    // pattern bytes as words, length PAT_WORDS
+    uint64_t *masks;          // per 64-y word: {squarefree bits, mu = -1 bits}
+    int64_t *mb;              // per word: M(y) just before the word's first y
+    int32_t *seg_sum;         // per segment: sum of mu
+    int64_t *seg_off;         // per segment: M(y) just before the segment
+    int64_t *carry;           // M(y1 - 1), advanced by the scan kernel
+};
+
+// The per-query state of one sweep (a batch of queries sharing the sieve).
+struct QueryArgs {
+    uint32_t nq;
+    const uint64_t *q_n, *q_L, *q_g0;   // per query: n, L, first global x index
+    // per global x index g (query q, x = g - q_g0[q] + 1)
+    uint64_t *x_m, *x_Y, *x_K, *x_k0;  // m = n/x, Y, K (k part end), k0
+    uint64_t *S;                        // wrapping uint64 contribution sums
+    int64_t *A;                         // final M(floor(n/x))
+    uint64_t *x_klo, *x_khi;            // k range of the current block
+    // tiles: 64 consecutive x of one query
+    uint32_t ntiles;
+    const uint32_t *tile_q, *tile_x0, *tile_nx;
+    const uint64_t *tile_g0;
+    uint64_t *tile_ymax;
+    // per-block work description
+    uint64_t *tile_klo, *tile_khi;
+    uint32_t *tile_mode, *tile_nmu;
+    uint64_t *tile_items;               // items per tile, then exclusive prefix (ntiles+1)
+    uint32_t *counter;                  // persistent work counter
+    uint64_t *pair_stats;               // [0] y-side visits, [1] k pairs
+    // tuning
+    double beta;
+    uint32_t ychunk, kchunk, klchunk;
+};
+
+// ---------------------------------------------------------------- launchers
+// All return the hipError_t of the launch (hipGetLastError()).
+hipError_t launch_zero_u64(uint64_t *p, size_t n, hipStream_t s);
+hipError_t launch_plan(const QueryArgs &q, hipStream_t s);
+hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s);
+hipError_t launch_sieve(const BlockArgs &b, hipStream_t s);
+hipError_t launch_scan_segments(const BlockArgs &b, hipStream_t s);
+hipError_t launch_fixup(const BlockArgs &b, hipStream_t s);
+hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
+hipError_t launch_scan_items(const QueryArgs &q, hipStream_t s);
+hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, hipStream_t s);
+hipError_t launch_finalize(const QueryArgs &q, hipStream_t s);
+hipError_t launch_collect(const QueryArgs &q, int64_t *out, hipStream_t s);
+hipError_t launch_debug_div(const uint64_t *n, const uint64_t *d, uint64_t *q, size_t count,
+                            hipStream_t s);
+hipError_t launch_debug_mu(const BlockArgs &b, uint64_t y_first, uint32_t count, int8_t *mu,
+                           int64_t *mert, hipStream_t s);
+
+// Host build of the device division routine (for tests without a GPU).
+void host_magic(uint32_t d, uint64_t *mul, uint32_t *sh1, uint32_t *sh2);
+uint64_t host_div(uint64_t n, uint64_t mul, uint32_t sh1, uint32_t sh2);
+
+}  // namespace mrt

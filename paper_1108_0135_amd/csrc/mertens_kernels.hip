@@ -1,0 +1,814 @@
+// HIP kernels (gfx950) of the exact Mertens method of arXiv:1108.0135.
+//
+// Section 2 of the paper: with A[x] = M(floor(n/x)) for x <= L = floor(n/u),
+// each A[x] = 1 - S[x] - sum_{k=2}^{floor(L/x)} A[kx], where S[x] collects
+// every term M(floor(m/k)), m = floor(n/x), whose argument is below u and
+// therefore comes from the sieve.  Section 3: y is swept in blocks; each
+// block is sieved (Moebius log-prime sieve), summed into M(y), and its
+// contributions are pushed into the S array; a final pass computes A.
+//
+// Per x the S sum is split at K = max(k0-1, floor(beta*sqrt(m)), floor(m/2^32))
+// with k0 = floor(L/x)+1 and Y = floor(m/(K+1)):
+//   explicit k part:   sum_{k=k0}^{K} M(floor(m/k))                  (gathers)
+//   run-length part:   sum_{y=1}^{Y-1} (floor(m/y)-floor(m/(y+1))) M(y)
+//                      + (floor(m/Y) - K) M(Y)
+// The run-length part is evaluated in its summed-by-parts form
+//   sum_{y=1}^{Y} floor(m/y) mu(y)  -  K M(Y),
+// the same integer (Abel summation of the run-length weights), which needs
+// mu(y) instead of M(y) and no multiply per pair.  All sums wrap mod 2^64.
+#include "mertens_internal.h"
+
+namespace mrt {
+
+// ====================================================================
+// Division by run-time invariant integers (Granlund & Montgomery, PLDI
+// 1994, Fig. 4.1, N = 64): for 1 <= d < 2^32,
+//   l = ceil(log2 d), mul = floor(2^64 (2^l - d) / d) + 1,
+//   floor(n/d) = (t + ((n - t) >> sh1)) >> sh2,  t = mulhi(mul, n),
+//   sh1 = min(l, 1), sh2 = max(l - 1, 0).
+// The paper (Section 3) replaces per-pair 64-bit division by such
+// multiply/shift sequences with per-divisor constants.
+// ====================================================================
+
+// floor(num / d) for num < d * 2^32 (quotient below 2^32), exact: an fp64
+// estimate within 2^-19 of the true quotient, then one correction step.
+__host__ __device__ inline uint64_t div_small_quot(uint64_t num, uint32_t d, uint64_t *rem)
+{
+    const double qd = (double)num / (double)d;
+    uint64_t q = (uint64_t)qd;
+    int64_t r = (int64_t)(num - q * (uint64_t)d);
+    if (r < 0) {
+        q -= 1;
+        r += d;
+    } else if (r >= (int64_t)d) {
+        q += 1;
+        r -= d;
+    }
+    *rem = (uint64_t)r;
+    return q;
+}
+
+__host__ __device__ inline void gm_magic(uint32_t d, uint64_t &mul, uint32_t &sh1, uint32_t &sh2)
+{
+    if (d <= 1) {  // d = 1 (d = 0 never divides; mapped to 1 harmlessly)
+        mul = 1;
+        sh1 = 0;
+        sh2 = 0;
+        return;
+    }
+#ifdef __HIP_DEVICE_COMPILE__
+    const uint32_t l = 32u - (uint32_t)__clz((int)(d - 1u));
+#else
+    const uint32_t l = 32u - (uint32_t)__builtin_clz(d - 1u);
+#endif
+    const uint64_t r = (l == 32 ? (1ull << 32) : (1ull << l)) - d;  // 2^l - d < d
+    uint64_t rem;
+    const uint64_t q1 = div_small_quot(r << 32, d, &rem);
+    const uint64_t q2 = div_small_quot(rem << 32, d, &rem);
+    mul = (q1 << 32) + q2 + 1;
+    sh1 = 1;
+    sh2 = l - 1;
+}
+
+__host__ __device__ inline uint64_t mulhi64(uint64_t a, uint64_t b)
+{
+#ifdef __HIP_DEVICE_COMPILE__
+    return __umul64hi(a, b);
+#else
+    return (uint64_t)(((unsigned __int128)a * b) >> 64);
+#endif
+}
+
+__host__ __device__ inline uint64_t gm_div(uint64_t n, uint64_t mul, uint32_t sh1, uint32_t sh2)
+{
+    const uint64_t t = mulhi64(mul, n);
+    return (t + ((n - t) >> sh1)) >> sh2;
+}
+
+void host_magic(uint32_t d, uint64_t *mul, uint32_t *sh1, uint32_t *sh2)
+{
+    gm_magic(d, *mul, *sh1, *sh2);
+}
+
+uint64_t host_div(uint64_t n, uint64_t mul, uint32_t sh1, uint32_t sh2)
+{
+    return gm_div(n, mul, sh1, sh2);
+}
+
+// ====================================================================
+// small device helpers
+// ====================================================================
+__device__ inline uint32_t lane_id() { return threadIdx.x & 63u; }
+
+__device__ inline uint64_t uniform_u64(uint64_t v)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t readlane_u64(uint64_t v, uint32_t lane)
+{
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)v, lane);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ inline uint64_t wave_min_u64(uint64_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint64_t t = __shfl_xor(v, o, 64);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+
+__device__ inline uint64_t wave_max_u64(uint64_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1) {
+        const uint64_t t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+__device__ inline uint64_t wave_sum_u64(uint64_t v)
+{
+    for (int o = 32; o >= 1; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// floor(sqrt(v)) for any uint64
+__device__ inline uint64_t isqrt64(uint64_t v)
+{
+    uint64_t r = (uint64_t)sqrt((double)v);
+    while (r > 0xFFFFFFFFull || r * r > v)
+        r--;
+    while (r < 0xFFFFFFFFull && (r + 1) * (r + 1) <= v)
+        r++;
+    return r;
+}
+
+// Exclusive scan of one int64 per thread across a workgroup of NT threads.
+template <int NT>
+__device__ inline int64_t wg_exclusive_scan(int64_t v, int64_t *wsum, int64_t &total)
+{
+    const uint32_t lane = lane_id(), wave = threadIdx.x >> 6;
+    int64_t x = v;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int64_t t = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o)
+            x += t;
+    }
+    if (lane == 63)
+        wsum[wave] = x;
+    __syncthreads();
+    int64_t pre = 0, tot = 0;
+    for (int k = 0; k < NT / 64; ++k) {
+        const int64_t s = wsum[k];
+        pre += (k < (int)wave) ? s : 0;
+        tot += s;
+    }
+    __syncthreads();
+    total = tot;
+    return pre + x - v;
+}
+
+// M(y) for y = y1 + off inside the current block: the word's prefix plus the
+// mu values of the word up to and including bit off mod 64.
+__device__ inline int64_t M_at(const uint64_t *__restrict__ masks, const int64_t *__restrict__ mb,
+                               uint64_t off)
+{
+    const uint64_t w = off >> 6;
+    const uint32_t b = (uint32_t)(off & 63);
+    const uint64_t lm = (2ull << b) - 1ull;  // bits 0..b (b = 63 wraps to all ones)
+    const uint64_t nz = masks[2 * w], ng = masks[2 * w + 1];
+    return mb[w] + (int64_t)__popcll(nz & lm) - 2 * (int64_t)__popcll(ng & lm);
+}
+
+// ====================================================================
+// generic small kernels
+// ====================================================================
+__global__ void k_zero_u64(uint64_t *p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n)
+        p[i] = 0;
+}
+
+hipError_t launch_zero_u64(uint64_t *p, size_t n, hipStream_t s)
+{
+    if (n == 0)
+        return hipSuccess;
+    const size_t grid = (n + 255) / 256;
+    hipLaunchKernelGGL(k_zero_u64, dim3((uint32_t)grid), dim3(256), 0, s, p, n);
+    return hipGetLastError();
+}
+
+// ====================================================================
+// a0: per-x plan.  One wave per tile, lane = x.
+// ====================================================================
+__global__ __launch_bounds__(UPD_THREADS) void k_plan(QueryArgs q)
+{
+    const uint32_t tile = blockIdx.x * (UPD_THREADS / 64) + (threadIdx.x >> 6);
+    const uint32_t lane = lane_id();
+    if (tile >= q.ntiles)
+        return;
+    const uint32_t qi = q.tile_q[tile];
+    const uint32_t nx = q.tile_nx[tile];
+    const bool valid = lane < nx;
+    uint64_t Y = 0, ysum = 0, ksum = 0;
+    if (valid) {
+        const uint64_t g = q.tile_g0[tile] + lane;
+        const uint64_t x = (uint64_t)q.tile_x0[tile] + lane;
+        const uint64_t n = q.q_n[qi], L = q.q_L[qi];
+        const uint64_t m = n / x;
+        const uint64_t k0 = L / x + 1;
+        uint64_t K = (uint64_t)(q.beta * (double)isqrt64(m));
+        if (K < k0 - 1)
+            K = k0 - 1;
+        if (K < (m >> 32))
+            K = m >> 32;
+        Y = m / (K + 1);
+        q.x_m[g] = m;
+        q.x_K[g] = K;
+        q.x_k0[g] = k0;
+        q.x_Y[g] = Y;
+        q.S[g] = 0;
+        ysum = Y;
+        ksum = K >= k0 ? K - k0 + 1 : 0;
+    }
+    const uint64_t ymax = wave_max_u64(Y);
+    ysum = wave_sum_u64(ysum);
+    ksum = wave_sum_u64(ksum);
+    if (lane == 0) {
+        q.tile_ymax[tile] = ymax;
+        atomicAdd((unsigned long long *)&q.pair_stats[0], (unsigned long long)ysum);
+        atomicAdd((unsigned long long *)&q.pair_stats[1], (unsigned long long)ksum);
+    }
+}
+
+hipError_t launch_plan(const QueryArgs &q, hipStream_t s)
+{
+    const uint32_t grid = (q.ntiles + 3) / 4;
+    hipLaunchKernelGGL(k_plan, dim3(grid), dim3(UPD_THREADS), 0, s, q);
+    return hipGetLastError();
+}
+
+// ====================================================================
+// a1: segmented Moebius block sieve (Section 3, modified algorithm).
+// ====================================================================
+// Per block: residues of y1 modulo every sieving prime and square.
+__global__ void k_block_setup(BlockArgs b)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n_sieve)
+        return;
+    const uint64_t p = b.primes[i];
+    b.res[i] = (uint32_t)(b.y1 % p);
+    if (i < b.n_sq)
+        b.res2[i] = b.y1 % (p * p);
+}
+
+hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s)
+{
+    if (b.n_sieve == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_block_setup, dim3((b.n_sieve + 255) / 256), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+// One workgroup per segment of SEG consecutive y.  LDS holds one byte per y:
+// bits 0-6 accumulate l_p = ceil(log2 p)|1 over sieving primes p | y, bit 7
+// flags a square divisor.  Four y share a 32-bit LDS word; sums stay below
+// 128 so bytes never carry into each other, and atomics make the prime
+// walks order-free.  Classification (corrected log rule, y >= 4):
+//   bit 7 set                        -> mu = 0
+//   A >= floor(log2 y) (fully split) -> mu = (-1)^A
+//   otherwise (one prime > Psieve)   -> mu = -(-1)^A
+// (A's parity is the number of sieving primes dividing y, as every l_p is
+// odd.)  The result is stored as two 64-bit masks per 64 y, plus exclusive
+// prefix sums of mu inside the segment.
+__global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b)
+{
+    __shared__ uint32_t lds[SEG / 4];
+    __shared__ int64_t wsum[SIEVE_THREADS / 64];
+    const uint32_t seg = blockIdx.x;
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t segbase = seg * SEG;  // < 2^31
+    const uint64_t s0 = b.y1 + segbase;
+
+    // pre-sieved pattern (2,3,5,7,11,13 and squares 4, 9)
+    uint32_t po = b.pat_off + segbase % PAT;
+    if (po >= PAT)
+        po -= PAT;
+    const uint32_t *src = b.pat32 + (po >> 2);  // po is a multiple of 4
+    for (uint32_t j = tid; j < SEG / 4; j += SIEVE_THREADS)
+        lds[j] = src[j];
+    __syncthreads();
+
+    // small primes: one wave per prime, lane i takes multiples i, i+64, ...
+    for (uint32_t i = FIRST_SIEVED + wave; i < b.n_small; i += SIEVE_THREADS / 64) {
+        const uint32_t p = b.primes[i];
+        const uint32_t lp = b.logp[i];
+        uint32_t r = b.res[i] + segbase % p;  // both < p < 2^10
+        if (r >= p)
+            r -= p;
+        const uint32_t first = r ? p - r : 0;
+        for (uint32_t o = first + lane * p; o < SEG; o += 64 * p)
+            atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
+    }
+    // larger primes: one lane per prime
+    for (uint32_t i = (b.n_small > FIRST_SIEVED ? b.n_small : FIRST_SIEVED) + tid; i < b.n_sieve;
+         i += SIEVE_THREADS) {
+        const uint32_t p = b.primes[i];
+        const uint32_t lp = b.logp[i];
+        uint64_t r = (uint64_t)b.res[i] + segbase % p;
+        if (r >= p)
+            r -= p;
+        const uint64_t first = r ? p - r : 0;
+        for (uint64_t o = first; o < SEG; o += p)
+            atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
+    }
+    // squares of primes >= 5
+    for (uint32_t i = tid; i < b.n_sq; i += SIEVE_THREADS) {
+        const uint64_t p = b.primes[i];
+        const uint64_t p2 = p * p;
+        uint64_t r = b.res2[i] + (p2 <= 0x80000000ull ? (uint64_t)(segbase % (uint32_t)p2)
+                                                       : (uint64_t)segbase);
+        if (r >= p2)
+            r -= p2;
+        const uint64_t first = r ? p2 - r : 0;
+        for (uint64_t o = first; o < SEG; o += p2)
+            atomicOr(&lds[o >> 2], 0x80u << ((o & 3u) << 3));
+    }
+    __syncthreads();
+
+    // classify: thread t owns words t and t + SIEVE_THREADS of the segment
+    int64_t cnt[2];
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t w = tid + (uint32_t)h * SIEVE_THREADS;
+        const uint64_t ybase = s0 + (uint64_t)w * 64;
+        const uint4 *l4 = reinterpret_cast<const uint4 *>(lds) + w * 4;
+        uint64_t nz = 0, ng = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint4 v = l4[j];
+            const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+            for (int g4 = 0; g4 < 4; ++g4) {
+                const uint32_t g = (uint32_t)(j * 4 + g4);
+                const uint64_t y = ybase + 4 * g;
+                uint32_t nzn, ngn;
+                if (y < 4) {
+                    nzn = 0xEu;  // mu(0..3) = 0, 1, -1, -1
+                    ngn = 0xCu;
+                } else {
+                    const uint32_t T = 63u - (uint32_t)__clzll((long long)y);  // floor(log2 y)
+                    const uint32_t x = vs[g4];
+                    const uint32_t F = ((x & 0x7f7f7f7fu) + (128u - T) * 0x01010101u) & 0x80808080u;
+                    const uint32_t par = (x & 0x01010101u) << 7;
+                    const uint32_t nzb = ~x & 0x80808080u;
+                    const uint32_t ngb = ~(F ^ par) & nzb;
+                    nzn = ((nzb >> 7) * 0x10204080u) >> 28;
+                    ngn = ((ngb >> 7) * 0x10204080u) >> 28;
+                }
+                nz |= (uint64_t)nzn << (4 * g);
+                ng |= (uint64_t)ngn << (4 * g);
+            }
+        }
+        const uint64_t gw = (uint64_t)seg * SEG_WORDS + w;
+        b.masks[2 * gw] = nz;
+        b.masks[2 * gw + 1] = ng;
+        cnt[h] = (int64_t)__popcll(nz) - 2 * (int64_t)__popcll(ng);
+    }
+    int64_t tot0, tot1;
+    const int64_t ex0 = wg_exclusive_scan<SIEVE_THREADS>(cnt[0], wsum, tot0);
+    const int64_t ex1 = wg_exclusive_scan<SIEVE_THREADS>(cnt[1], wsum, tot1);
+    const uint64_t gw0 = (uint64_t)seg * SEG_WORDS + tid;
+    b.mb[gw0] = ex0;
+    b.mb[gw0 + SIEVE_THREADS] = tot0 + ex1;
+    if (tid == 0)
+        b.seg_sum[seg] = (int32_t)(tot0 + tot1);
+}
+
+hipError_t launch_sieve(const BlockArgs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_sieve, dim3(b.nseg), dim3(SIEVE_THREADS), 0, s, b);
+    return hipGetLastError();
+}
+
+// ====================================================================
+// a2: M(y) prefix scan across the segments of a block, carrying M(y1-1).
+// ====================================================================
+constexpr int SCAN_THREADS = 1024;
+
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_segments(BlockArgs b)
+{
+    __shared__ int64_t wsum[SCAN_THREADS / 64];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (b.nseg + SCAN_THREADS - 1) / SCAN_THREADS;
+    const uint32_t s_begin = tid * per;
+    const uint32_t s_end = (s_begin + per < b.nseg) ? s_begin + per : b.nseg;
+    int64_t local = 0;
+    for (uint32_t sgi = s_begin; sgi < s_end; ++sgi)
+        local += b.seg_sum[sgi];
+    const int64_t carry = *b.carry;
+    int64_t total;
+    const int64_t ex = wg_exclusive_scan<SCAN_THREADS>(local, wsum, total);
+    int64_t run = carry + ex;
+    for (uint32_t sgi = s_begin; sgi < s_end; ++sgi) {
+        b.seg_off[sgi] = run;
+        run += b.seg_sum[sgi];
+    }
+    __syncthreads();
+    if (tid == 0)
+        *b.carry = carry + total;
+}
+
+__global__ void k_fixup(BlockArgs b)
+{
+    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w < (uint64_t)b.nseg * SEG_WORDS)
+        b.mb[w] += b.seg_off[w / SEG_WORDS];
+}
+
+hipError_t launch_scan_segments(const BlockArgs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(SCAN_THREADS), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_fixup(const BlockArgs &b, hipStream_t s)
+{
+    const uint64_t words = (uint64_t)b.nseg * SEG_WORDS;
+    hipLaunchKernelGGL(k_fixup, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+// ====================================================================
+// a3: per-block contribution update.
+// ====================================================================
+// Prep: per x, the k range whose quotients floor(m/k) land in [y1, y2]; the
+// one-off term -K*M(Y) when Y is in this block; per tile, the number of
+// work items of the run-length part and of the explicit k part.
+__global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockArgs b)
+{
+    const uint32_t tile = blockIdx.x * (UPD_THREADS / 64) + (threadIdx.x >> 6);
+    const uint32_t lane = lane_id();
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+        *q.counter = 0;
+    if (tile >= q.ntiles)
+        return;
+    const uint32_t nx = q.tile_nx[tile];
+    const uint64_t g = q.tile_g0[tile] + lane;
+    const uint64_t y1e = b.y1 > 0 ? b.y1 : 1;
+    uint64_t klo = 1, khi = 0;
+    if (lane < nx) {
+        const uint64_t m = q.x_m[g], K = q.x_K[g], k0 = q.x_k0[g], Y = q.x_Y[g];
+        uint64_t lo = m / (b.y2 + 1) + 1;
+        if (lo < k0)
+            lo = k0;
+        uint64_t hi = m / y1e;
+        if (hi > K)
+            hi = K;
+        if (lo <= hi) {
+            klo = lo;
+            khi = hi;
+        }
+        q.x_klo[g] = klo;
+        q.x_khi[g] = khi;
+        if (Y >= y1e && Y <= b.y2)
+            q.S[g] -= K * (uint64_t)M_at(b.masks, b.mb, Y - b.y1);
+    }
+    const bool has = klo <= khi;
+    const uint64_t tmin = wave_min_u64(has ? klo : ~0ull);
+    const uint64_t tmax = wave_max_u64(has ? khi : 0ull);
+    const uint64_t mlen = wave_max_u64(has ? khi - klo + 1 : 0ull);
+    if (lane == 0) {
+        uint64_t nk = 0;
+        uint32_t mode = 0;
+        if (mlen > 0) {
+            const uint64_t uni = tmax - tmin + 1;
+            if (uni <= 4 * mlen) {
+                mode = 0;
+                nk = (uni + q.kchunk - 1) / q.kchunk;
+            } else {
+                mode = 1;
+                nk = (mlen + q.klchunk - 1) / q.klchunk;
+            }
+        }
+        q.tile_klo[tile] = tmin;
+        q.tile_khi[tile] = tmax;
+        q.tile_mode[tile] = mode;
+        const uint64_t yb = q.tile_ymax[tile] < b.y2 ? q.tile_ymax[tile] : b.y2;
+        const uint64_t yal = y1e & ~63ull;
+        const uint64_t nmu = yb >= y1e ? (yb - yal) / q.ychunk + 1 : 0;
+        q.tile_nmu[tile] = (uint32_t)nmu;
+        q.tile_items[tile] = nmu + nk;
+    }
+}
+
+hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s)
+{
+    const uint32_t grid = (q.ntiles + 3) / 4;
+    hipLaunchKernelGGL(k_update_prep, dim3(grid), dim3(UPD_THREADS), 0, s, q, b);
+    return hipGetLastError();
+}
+
+// In-place exclusive prefix of tile_items (ntiles entries); total at [ntiles].
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_items(QueryArgs q)
+{
+    __shared__ int64_t wsum[SCAN_THREADS / 64];
+    const uint32_t tid = threadIdx.x;
+    const uint32_t per = (q.ntiles + SCAN_THREADS - 1) / SCAN_THREADS;
+    const uint32_t t0 = tid * per;
+    const uint32_t t1 = (t0 + per < q.ntiles) ? t0 + per : q.ntiles;
+    int64_t local = 0;
+    for (uint32_t t = t0; t < t1; ++t)
+        local += (int64_t)q.tile_items[t];
+    int64_t total;
+    const int64_t ex = wg_exclusive_scan<SCAN_THREADS>(local, wsum, total);
+    int64_t run = ex;
+    for (uint32_t t = t0; t < t1; ++t) {
+        const int64_t v = (int64_t)q.tile_items[t];
+        q.tile_items[t] = (uint64_t)run;
+        run += v;
+    }
+    if (tid == 0)
+        q.tile_items[q.ntiles] = (uint64_t)total;
+}
+
+hipError_t launch_scan_items(const QueryArgs &q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_items, dim3(1), dim3(SCAN_THREADS), 0, s, q);
+    return hipGetLastError();
+}
+
+// Largest t < ntiles with prefix[t] <= item (wave-parallel 64-ary search).
+__device__ inline uint32_t find_tile(const uint64_t *__restrict__ prefix, uint32_t ntiles,
+                                     uint64_t item)
+{
+    const uint32_t lane = lane_id();
+    uint32_t lo = 0, hi = ntiles;
+    while (hi - lo > 1) {
+        const uint32_t stride = (hi - lo + 63) / 64;
+        const uint32_t idx = lo + lane * stride;
+        const bool ok = idx < hi && prefix[idx] <= item;
+        const uint64_t bal = __ballot(ok);
+        const uint32_t j = 63u - (uint32_t)__clzll((long long)bal);
+        lo = lo + j * stride;
+        const uint32_t nhi = lo + stride;
+        hi = nhi < hi ? nhi : hi;
+    }
+    return lo;
+}
+
+// Run-length part of one (tile, y-chunk) item:
+//   S[x] += sum_{y in chunk, y <= Y_x, mu(y) != 0} mu(y) floor(m_x / y).
+// y is uniform across the wave (lane = x): the mask words come from scalar
+// loads, the 64 divisor constants of a word are computed one per lane and
+// broadcast with readlane.
+__device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t tile, uint64_t c)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t nx = q.tile_nx[tile];
+    const uint64_t g = q.tile_g0[tile] + lane;
+    const bool valid = lane < nx;
+    const uint64_t m = valid ? q.x_m[g] : 0;
+    const uint64_t Y = valid ? q.x_Y[g] : 0;
+    const uint64_t y1e = b.y1 > 0 ? b.y1 : 1;
+    const uint64_t tymax = uniform_u64(q.tile_ymax[tile]);
+    const uint64_t yb_t = tymax < b.y2 ? tymax : b.y2;
+    const uint64_t yal = y1e & ~63ull;
+    uint64_t cs = yal + c * q.ychunk;
+    uint64_t ce = cs + q.ychunk - 1;
+    if (ce > yb_t)
+        ce = yb_t;
+    if (cs < y1e)
+        cs = y1e;
+    uint64_t acc = 0;
+    for (uint64_t wbase = cs & ~63ull; wbase <= ce; wbase += 64) {
+        const uint64_t woff = (wbase - b.y1) >> 6;
+        const uint64_t nz = uniform_u64(b.masks[2 * woff]);
+        const uint64_t ng = uniform_u64(b.masks[2 * woff + 1]);
+        const uint32_t lob = wbase < cs ? (uint32_t)(cs - wbase) : 0u;
+        const uint32_t hib = (ce - wbase) < 63 ? (uint32_t)(ce - wbase) : 63u;
+        uint64_t bits = nz & (~0ull << lob) & ((2ull << hib) - 1ull);
+        if (bits == 0)
+            continue;
+        uint64_t mul;
+        uint32_t sh1, sh2;
+        gm_magic((uint32_t)(wbase + lane), mul, sh1, sh2);
+        while (bits) {
+            const uint32_t bt = (uint32_t)__builtin_ctzll(bits);
+            bits &= bits - 1;
+            const uint64_t y = wbase + bt;
+            const uint64_t mg = readlane_u64(mul, bt);
+            const uint32_t s1 = __builtin_amdgcn_readlane(sh1, bt);
+            const uint32_t s2 = __builtin_amdgcn_readlane(sh2, bt);
+            const uint64_t qv = gm_div(m, mg, s1, s2);
+            if (y <= Y) {
+                if ((ng >> bt) & 1ull)
+                    acc -= qv;
+                else
+                    acc += qv;
+            }
+        }
+    }
+    if (valid)
+        atomicAdd((unsigned long long *)&q.S[g], (unsigned long long)acc);
+}
+
+// Explicit k part of one (tile, k-chunk) item: S[x] += M(floor(m_x / k)) for
+// k in the chunk and in x's range [klo, khi] of this block.
+__device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t tile, uint64_t c)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t nx = q.tile_nx[tile];
+    const uint64_t g = q.tile_g0[tile] + lane;
+    const bool valid = lane < nx;
+    const uint64_t m = valid ? q.x_m[g] : 0;
+    const uint64_t klo = valid ? q.x_klo[g] : 1;
+    const uint64_t khi = valid ? q.x_khi[g] : 0;
+    uint64_t acc = 0;
+    if (__builtin_amdgcn_readfirstlane(q.tile_mode[tile]) == 0) {
+        // uniform k across the wave
+        const uint64_t kb = uniform_u64(q.tile_klo[tile]) + c * q.kchunk;
+        const uint64_t tkhi = uniform_u64(q.tile_khi[tile]);
+        uint64_t ke = kb + q.kchunk - 1;
+        if (ke > tkhi)
+            ke = tkhi;
+        for (uint64_t kk = kb; kk <= ke; kk += 64) {
+            uint64_t mul;
+            uint32_t sh1, sh2;
+            gm_magic((uint32_t)(kk + lane), mul, sh1, sh2);
+            const uint32_t jmax = (ke - kk) < 63 ? (uint32_t)(ke - kk) : 63u;
+            for (uint32_t j = 0; j <= jmax; ++j) {
+                const uint64_t k = kk + j;
+                const uint64_t mg = readlane_u64(mul, j);
+                const uint32_t s1 = __builtin_amdgcn_readlane(sh1, j);
+                const uint32_t s2 = __builtin_amdgcn_readlane(sh2, j);
+                if (k >= klo && k <= khi) {
+                    const uint64_t y = gm_div(m, mg, s1, s2);
+                    acc += (uint64_t)M_at(b.masks, b.mb, y - b.y1);
+                }
+            }
+        }
+    } else {
+        // each lane walks its own sub-range
+        const uint64_t ks = klo + c * q.klchunk;
+        uint64_t ke = ks + q.klchunk - 1;
+        if (ke > khi)
+            ke = khi;
+        for (uint64_t k = ks; k <= ke && klo <= khi; ++k) {
+            const uint64_t y = m / k;
+            acc += (uint64_t)M_at(b.masks, b.mb, y - b.y1);
+        }
+    }
+    if (valid)
+        atomicAdd((unsigned long long *)&q.S[g], (unsigned long long)acc);
+}
+
+// Persistent update kernel of one block: every wave takes work items from
+// a device counter until the block's items are exhausted.
+__global__ __launch_bounds__(UPD_THREADS) void k_update(QueryArgs q, BlockArgs b)
+{
+    const uint32_t lane = lane_id();
+    const uint64_t total = q.tile_items[q.ntiles];
+    for (;;) {
+        uint32_t it = 0;
+        if (lane == 0)
+            it = atomicAdd(q.counter, 1u);
+        const uint64_t item = __shfl(it, 0, 64);
+        if (item >= total)
+            break;
+        const uint32_t tile =
+            __builtin_amdgcn_readfirstlane(find_tile(q.tile_items, q.ntiles, item));
+        const uint64_t local = uniform_u64(item - q.tile_items[tile]);
+        const uint32_t nmu = __builtin_amdgcn_readfirstlane(q.tile_nmu[tile]);
+        if (local < nmu)
+            mu_item(q, b, tile, local);
+        else
+            k_item(q, b, tile, local - nmu);
+    }
+}
+
+hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_update, dim3(grid), dim3(UPD_THREADS), 0, s, q, b);
+    return hipGetLastError();
+}
+
+// ====================================================================
+// a4: finalize.  A[x] = 1 - S[x] - sum_{k=2}^{floor(L/x)} A[kx], for x from
+// L down to 1 (Section 2), one workgroup per query.  All x with the same
+// j = floor(L/x) form one level whose dependencies lie in earlier levels.
+// ====================================================================
+constexpr int FIN_THREADS = 1024;
+
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(QueryArgs q)
+{
+    const uint32_t qi = blockIdx.x;
+    const uint64_t L = q.q_L[qi];
+    const uint64_t g0 = q.q_g0[qi];
+    const uint64_t *S = q.S + g0;
+    uint64_t *A = reinterpret_cast<uint64_t *>(q.A + g0);  // A[x-1], wrapping arithmetic
+    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    uint64_t xh = L;
+    while (xh >= 1) {
+        const uint64_t j = L / xh;
+        const uint64_t xl = L / (j + 1);
+        const uint64_t cnt = xh - xl;
+        if (cnt >= 256 || j == 1) {
+            for (uint64_t x = xl + 1 + tid; x <= xh; x += FIN_THREADS) {
+                uint64_t s = 1 - S[x - 1];
+                for (uint64_t k = 2; k <= j; ++k)
+                    s -= A[k * x - 1];
+                A[x - 1] = s;
+            }
+        } else {
+            for (uint64_t x = xl + 1 + wave; x <= xh; x += FIN_THREADS / 64) {
+                uint64_t s = 0;
+                for (uint64_t k = 2 + lane; k <= j; k += 64)
+                    s += A[k * x - 1];
+                s = wave_sum_u64(s);
+                if (lane == 0)
+                    A[x - 1] = 1 - S[x - 1] - s;
+            }
+        }
+        __syncthreads();
+        xh = xl;
+    }
+}
+
+hipError_t launch_finalize(const QueryArgs &q, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize, dim3(q.nq), dim3(FIN_THREADS), 0, s, q);
+    return hipGetLastError();
+}
+
+__global__ void k_collect(QueryArgs q, int64_t *out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < q.nq)
+        out[i] = q.A[q.q_g0[i]];
+}
+
+hipError_t launch_collect(const QueryArgs &q, int64_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_collect, dim3((q.nq + 255) / 256), dim3(256), 0, s, q, out);
+    return hipGetLastError();
+}
+
+// ====================================================================
+// diagnostics
+// ====================================================================
+__global__ void k_debug_div(const uint64_t *n, const uint64_t *d, uint64_t *qo, size_t count)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count)
+        return;
+    uint64_t mul;
+    uint32_t sh1, sh2;
+    gm_magic((uint32_t)d[i], mul, sh1, sh2);
+    qo[i] = gm_div(n[i], mul, sh1, sh2);
+}
+
+hipError_t launch_debug_div(const uint64_t *n, const uint64_t *d, uint64_t *q, size_t count,
+                            hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_debug_div, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s, n, d,
+                       q, count);
+    return hipGetLastError();
+}
+
+// mu(y) and M(y) (relative to the block's carry) for y in [y_first, y_first+count)
+__global__ void k_debug_mu(BlockArgs b, uint64_t y_first, uint32_t count, int8_t *mu, int64_t *mert)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= count)
+        return;
+    const uint64_t off = y_first + i - b.y1;
+    const uint64_t w = off >> 6;
+    const uint32_t bt = (uint32_t)(off & 63);
+    const uint64_t nz = b.masks[2 * w], ng = b.masks[2 * w + 1];
+    mu[i] = ((nz >> bt) & 1) ? (((ng >> bt) & 1) ? -1 : 1) : 0;
+    if (mert)
+        mert[i] = M_at(b.masks, b.mb, off);
+}
+
+hipError_t launch_debug_mu(const BlockArgs &b, uint64_t y_first, uint32_t count, int8_t *mu,
+                           int64_t *mert, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_debug_mu, dim3((count + 255) / 256), dim3(256), 0, s, b, y_first, count,
+                       mu, mert);
+    return hipGetLastError();
+}
+
+}  // namespace mrt

@@ -1,0 +1,139 @@
+"""Thin ctypes binding of libmertens.so (the C ABI in include/mertens.h).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI.  There is no fallback; if the library is missing
+the import of this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libmertens.so")
+HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "mertens.h")
+
+EINVAL, ENOMEM, ENODEV, ERANGE, EIO, EAGAIN, EINPROGRESS = -22, -12, -19, -34, -5, -11, -115
+
+STAT_NAMES = ["sieved_y", "blocks", "u", "sum_L", "rl_pairs", "k_pairs", "ms_sieve",
+              "ms_scan", "ms_prep", "ms_update", "ms_finalize", "ms_total", "update_launches",
+              "sieve_launches"]
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1108_0135_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+_u64, _i64, _sz = ctypes.c_uint64, ctypes.c_int64, ctypes.c_size_t
+_P = ctypes.POINTER
+_sig = {
+    "mertens_init": ([_u64, _u64], ctypes.c_int),
+    "mertens_query": ([_P(_u64), _sz, _P(_i64)], ctypes.c_int),
+    "mertens_byproducts": ([_sz, _P(_i64), _sz, _P(_sz)], ctypes.c_int),
+    "mertens_set_stream": ([ctypes.c_void_p], ctypes.c_int),
+    "mertens_set_param": ([ctypes.c_char_p, ctypes.c_double], ctypes.c_int),
+    "mertens_stats": ([_P(ctypes.c_double), ctypes.c_int], ctypes.c_int),
+    "mertens_shutdown": ([], None),
+    "mertens_strerror": ([ctypes.c_int], ctypes.c_char_p),
+    "mertens_last_error": ([], ctypes.c_char_p),
+    "mertens_debug_div": ([_P(_u64), _P(_u64), _sz, _P(_u64), ctypes.c_int], ctypes.c_int),
+    "mertens_debug_mu": ([_u64, _sz, _P(ctypes.c_int8), _P(_i64)], ctypes.c_int),
+}
+for _name, (_args, _ret) in _sig.items():
+    _f = getattr(_lib, _name)
+    _f.argtypes = _args
+    _f.restype = _ret
+
+
+class MertensError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.mertens_strerror(code).decode()
+        detail = _lib.mertens_last_error().decode()
+        super().__init__(f"{where}: {msg} ({code}); {detail}")
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != 0:
+        raise MertensError(rc, where)
+
+
+def _u64p(a: np.ndarray):
+    return a.ctypes.data_as(_P(_u64))
+
+
+def _i64p(a: np.ndarray):
+    return a.ctypes.data_as(_P(_i64))
+
+
+def header_symbols() -> list[str]:
+    """Every function the public header declares."""
+    text = open(HEADER_PATH).read()
+    return sorted(set(re.findall(r"^\s*(?:int|void|const char \*)\s*(mertens_\w+)\s*\(", text, re.M)))
+
+
+def init(u: int = 0, block: int = 0) -> None:
+    _check(_lib.mertens_init(u, block), "mertens_init")
+
+
+def shutdown() -> None:
+    _lib.mertens_shutdown()
+
+
+def query(ns) -> np.ndarray:
+    """Exact M(n) for every n (uint64-representable), one shared sweep."""
+    arr = np.ascontiguousarray(np.asarray(ns, dtype=np.uint64).reshape(-1))
+    out = np.zeros(arr.size, dtype=np.int64)
+    _check(_lib.mertens_query(_u64p(arr), arr.size, _i64p(out)), "mertens_query")
+    return out
+
+
+def byproducts(i: int, cap: int | None = None) -> np.ndarray:
+    """[M(floor(n_i/c)) for c = 1..L] of query i of the last call."""
+    n = _sz(0)
+    if cap is None:
+        _check(_lib.mertens_byproducts(i, None, 0, ctypes.byref(n)), "mertens_byproducts")
+        cap = n.value
+    buf = np.zeros(max(cap, 1), dtype=np.int64)
+    _check(_lib.mertens_byproducts(i, _i64p(buf), cap, ctypes.byref(n)), "mertens_byproducts")
+    return buf[: min(cap, n.value)]
+
+
+def set_param(key: str, value: float) -> None:
+    _check(_lib.mertens_set_param(key.encode(), float(value)), f"mertens_set_param({key})")
+
+
+def set_stream(stream_handle: int | None) -> None:
+    """Run on a HIP stream given as an integer handle (e.g. torch's cuda_stream)."""
+    _check(_lib.mertens_set_stream(ctypes.c_void_p(stream_handle or 0)), "mertens_set_stream")
+
+
+def stats() -> dict:
+    vals = (ctypes.c_double * len(STAT_NAMES))()
+    k = _lib.mertens_stats(vals, len(STAT_NAMES))
+    return {STAT_NAMES[i]: vals[i] for i in range(k)}
+
+
+def debug_div(n, d, on_device: bool) -> np.ndarray:
+    na = np.ascontiguousarray(np.asarray(n, dtype=np.uint64))
+    da = np.ascontiguousarray(np.asarray(d, dtype=np.uint64))
+    assert na.shape == da.shape
+    q = np.zeros(na.size, dtype=np.uint64)
+    _check(_lib.mertens_debug_div(_u64p(na), _u64p(da), na.size, _u64p(q), int(on_device)),
+           "mertens_debug_div")
+    return q
+
+
+def debug_mu(y1: int, count: int, with_sums: bool = True):
+    mu = np.zeros(count, dtype=np.int8)
+    sums = np.zeros(count, dtype=np.int64) if with_sums else None
+    _check(_lib.mertens_debug_mu(y1, count, mu.ctypes.data_as(_P(ctypes.c_int8)),
+                                 _i64p(sums) if with_sums else None), "mertens_debug_mu")
+    return mu, sums
+
+
+def raw():
+    """The ctypes library handle (tests use it to probe error returns)."""
+    return _lib

@@ -1,0 +1,56 @@
+"""Write the stored expected values used by the GPU parity tests.
+
+Calls only the CPU oracle (``oracle/``) on the seeded inputs of
+``paper_1108_0135_amd.inputs``; never the GPU path.  Re-run after any change
+to the oracle's arithmetic:  python tests/golden/make_golden.py
+"""
+from __future__ import annotations
+
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+from paper_1108_0135_amd import inputs  # noqa: E402
+
+
+def main() -> None:
+    t0 = time.time()
+    out = {"generator": "tests/golden/make_golden.py (oracle only)"}
+
+    # the brute-force-checkable set: 32 n uniform in [2, 1e9], seed 0 (O1 sweep)
+    ns = inputs.uniform_small(seed=0, count=32)
+    out["seeded32"] = {"seed": 0, "n": [int(v) for v in ns],
+                       "M": [int(v) for v in oracle.mertens_many(ns)]}
+
+    # n = 1e12 and every byproduct M(floor(n/c)), c <= 1e4 (O2 on an O1 table to 1e8)
+    o2 = oracle.IdentityOracle(10**8)
+    m, byp = o2.query(10**12, 10**4)
+    out["n1e12"] = {"n": 10**12, "L": 10**4, "M": m, "byproducts": [int(v) for v in byp]}
+
+    # n = 1e16, u = 5e10 (L = 2e5): sampled byproducts c in [1e4, 2e5] that O2 reaches
+    rng = np.random.default_rng(5)
+    cs = sorted({int(c) for c in rng.integers(10**4, 2 * 10**5 + 1, 12)} | {10**4, 2 * 10**5})
+    out["n1e16_samples"] = {"n": 10**16, "c": cs,
+                            "M": [o2.query(10**16 // c)[0] for c in cs]}
+
+    # a mixed batch: 48 n log-uniform in [1e3, 1e11], seed 1
+    nb = inputs.log_uniform(1, 48, 1e3, 1e11)
+    out["batch48"] = {"seed": 1, "n": [int(v) for v in nb],
+                      "M": [o2.query(int(v))[0] for v in nb]}
+
+    path = os.path.join(HERE, "golden.json")
+    with open(path, "w") as f:
+        json.dump(out, f)
+    print(f"wrote {path} in {time.time() - t0:.1f} s")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,85 @@
+"""CPU-side checks of the C ABI: the library loads, exports every declared
+symbol, rejects bad arguments, and its host build of the division routine
+is exact (no GPU needed for any of these)."""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import pytest
+
+from paper_1108_0135_amd import mertens as mt
+
+
+def test_exports_every_header_symbol():
+    syms = mt.header_symbols()
+    assert len(syms) >= 11
+    lib = ctypes.CDLL(mt.LIB_PATH)
+    for s in syms:
+        assert hasattr(lib, s), s
+
+
+def test_strerror_codes():
+    lib = mt.raw()
+    for code in (0, mt.EINVAL, mt.ENOMEM, mt.ENODEV, mt.ERANGE, mt.EIO, mt.EAGAIN,
+                 mt.EINPROGRESS):
+        assert lib.mertens_strerror(code)
+    assert lib.mertens_strerror(-9999) == b"unknown error"
+
+
+def test_bad_arguments_without_gpu():
+    lib = mt.raw()
+    # invalid block sizes are rejected before any device call
+    for blk in (1, 65535, 65536 + 64, (1 << 31) + 65536):
+        assert lib.mertens_init(0, blk) == mt.EINVAL
+    # count 0 touches nothing; null pointers with count > 0 are rejected
+    assert lib.mertens_query(None, 0, None) == 0
+    assert lib.mertens_query(None, 3, None) == mt.EINVAL
+    assert lib.mertens_set_param(b"nope", 1.0) == mt.EINVAL
+    assert lib.mertens_set_param(b"beta", 0.0) == mt.EINVAL
+    assert lib.mertens_set_param(b"ychunk", 100.0) == mt.EINVAL  # not a multiple of 64
+    # divisor outside [1, 2^32)
+    n = np.array([5], dtype=np.uint64)
+    for bad in (0, 1 << 32):
+        d = np.array([bad], dtype=np.uint64)
+        q = np.zeros(1, dtype=np.uint64)
+        assert lib.mertens_debug_div(mt._u64p(n), mt._u64p(d), 1, mt._u64p(q), 0) == mt.EINVAL
+
+
+def test_no_device_here_or_initialised():
+    # on a host without a GPU, init reports ENODEV and queries refuse to run
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    lib = mt.raw()
+    assert lib.mertens_init(0, 0) == mt.ENODEV
+    n = np.array([10], dtype=np.uint64)
+    out = np.zeros(1, dtype=np.int64)
+    assert lib.mertens_query(mt._u64p(n), 1, mt._i64p(out)) == mt.ENODEV
+
+
+def _div_cases(rng):
+    ds, ns = [], []
+    M64 = (1 << 64) - 1
+    # every d <= 2^12 and powers of two / neighbours, at quotient boundaries
+    dlist = list(range(1, 4097)) + [2**k + e for k in range(12, 32) for e in (-1, 0, 1)]
+    dlist += [int(v) for v in rng.integers(1, 1 << 32, 2000)]
+    dlist = [d for d in dlist if 1 <= d < (1 << 32)]
+    for d in dlist:
+        qs = [int(rng.integers(0, M64 // d + 1, dtype=np.uint64)), M64 // d, 1, 0]
+        for q in qs:
+            for n in (q * d - 1, q * d, q * d + d - 1):
+                if 0 <= n <= M64:
+                    ds.append(d)
+                    ns.append(n)
+        ds.append(d)
+        ns.append(M64)
+    return np.array(ns, dtype=np.uint64), np.array(ds, dtype=np.uint64)
+
+
+def test_gm_division_host_exact():
+    rng = np.random.default_rng(3)
+    n, d = _div_cases(rng)
+    q = mt.debug_div(n, d, on_device=False)
+    ref = np.array([int(a) // int(b) for a, b in zip(n, d)], dtype=np.uint64)
+    assert np.array_equal(q, ref)

@@ -1,0 +1,151 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle.
+
+Everything is exact integer work, so every comparison is bit-exact.
+Expected values come from the oracle at test time (small cases) or from
+tests/golden/golden.json, written by tests/golden/make_golden.py, which
+calls only the oracle.  Printed values of the paper (Table 1) are pinned
+directly.
+"""
+from __future__ import annotations
+
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1108_0135_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "golden.json")))
+
+
+@pytest.fixture(scope="module")
+def mt():
+    from paper_1108_0135_amd import mertens as mt
+    mt.init(0, 0)
+    yield mt
+    mt.shutdown()
+
+
+def _reinit(mt, u=0, block=0, **params):
+    mt.init(u, block)
+    for k, v in params.items():
+        mt.set_param(k, v)
+
+
+# ------------------------------------------------------------------ division
+
+def test_gm_division_device(mt):
+    from tests.test_abi import _div_cases
+    rng = np.random.default_rng(4)
+    n, d = _div_cases(rng)
+    q = mt.debug_div(n, d, on_device=True)
+    ref = np.array([int(a) // int(b) for a, b in zip(n, d)], dtype=np.uint64)
+    assert np.array_equal(q, ref)
+
+
+# ------------------------------------------------------------------ sieve + scan
+
+def test_sieve_mu_and_M_from_zero(mt):
+    _reinit(mt)
+    N = (1 << 21) + 12345
+    mu, sums = mt.debug_mu(0, N + 1)
+    assert np.array_equal(mu, oracle.mu_range(0, N))
+    assert np.array_equal(sums, oracle.mertens_table(N).astype(np.int64))
+
+
+@pytest.mark.parametrize("y1", [10**9 - 70_000, 2**40 - 1000, 10**12 + 7, 10**15 - 200_001,
+                                11609864264058592345 // 1000])
+def test_sieve_windows(mt, y1):
+    count = 300_000
+    mu, sums = mt.debug_mu(y1, count)
+    ref = oracle.mu_range(y1, y1 + count - 1)
+    assert np.array_equal(mu, ref)
+    assert np.array_equal(sums, np.cumsum(ref.astype(np.int64)))
+
+
+# ------------------------------------------------------------------ M(n)
+
+def test_small_n_every_value(mt):
+    _reinit(mt)
+    ns = np.arange(0, 3001, dtype=np.uint64)
+    got = mt.query(ns)
+    assert np.array_equal(got, oracle.mertens_table(3000).astype(np.int64))
+
+
+@pytest.mark.parametrize("u", [2, 7, 100, 10**4])
+def test_small_n_fixed_u(mt, u):
+    _reinit(mt, u=u, block=1 << 16)
+    ns = np.arange(1, 2001, dtype=np.uint64)
+    assert np.array_equal(mt.query(ns), oracle.mertens_table(2000)[1:].astype(np.int64))
+
+
+def test_seeded32(mt):
+    _reinit(mt)
+    g = GOLDEN["seeded32"]
+    assert g["n"] == [int(v) for v in inputs.uniform_small(seed=g["seed"], count=32)]
+    assert list(mt.query(g["n"])) == g["M"]
+
+
+def test_seeded32_one_at_a_time(mt):
+    _reinit(mt)
+    g = GOLDEN["seeded32"]
+    got = [int(mt.query([n])[0]) for n in g["n"][:8]]
+    assert got == g["M"][:8]
+
+
+def test_n1e12_and_byproducts(mt):
+    g = GOLDEN["n1e12"]
+    _reinit(mt, u=10**8)
+    assert int(mt.query([g["n"]])[0]) == g["M"]
+    byp = mt.byproducts(0)
+    assert byp.size == g["L"]
+    assert list(byp) == g["byproducts"]
+
+
+@pytest.mark.parametrize("u,block,params", [
+    (10**8, 1 << 16, {}),
+    (3 * 10**7, 1 << 20, {"beta": 1.0}),
+    (2 * 10**8, 1 << 24, {"beta": 0.25, "ychunk": 64, "kchunk": 64}),
+    (10**8, 1 << 26, {"ychunk": 1 << 16, "kchunk": 1 << 15, "klchunk": 1}),
+])
+def test_n1e12_invariance(mt, u, block, params):
+    g = GOLDEN["n1e12"]
+    _reinit(mt, u=u, block=block, **params)
+    assert int(mt.query([g["n"]])[0]) == g["M"]
+    byp = mt.byproducts(0)
+    L = byp.size
+    assert list(byp) == [int(v) for v in g["byproducts"][:L]] or L > g["L"]
+    if L > g["L"]:
+        assert list(byp[: g["L"]]) == g["byproducts"]
+
+
+def test_batch48(mt):
+    _reinit(mt)
+    g = GOLDEN["batch48"]
+    assert list(mt.query(g["n"])) == g["M"]
+
+
+def test_batch_is_order_and_composition_free(mt):
+    _reinit(mt, u=10**8)
+    g = GOLDEN["batch48"]
+    ns = g["n"] + [10**12, 10**12, 0, 1]
+    exp = g["M"] + [GOLDEN["n1e12"]["M"]] * 2 + [0, 1]
+    perm = np.random.default_rng(9).permutation(len(ns))
+    got = mt.query([ns[i] for i in perm])
+    assert [int(v) for v in got] == [exp[i] for i in perm]
+
+
+def test_table1_1e16(mt):
+    # Table 1 of the paper: M(10^16) = -3195437; byproducts against the oracle
+    _reinit(mt, u=5 * 10**10, block=1 << 30)
+    assert int(mt.query([10**16])[0]) == inputs.TABLE1[10**16]
+    g = GOLDEN["n1e16_samples"]
+    byp = mt.byproducts(0)
+    assert byp.size == 2 * 10**5
+    assert [int(byp[c - 1]) for c in g["c"]] == g["M"]
+    st = mt.stats()
+    assert st["blocks"] == 47 and st["sieved_y"] == 10**16 // (2 * 10**5 + 1) + 1
