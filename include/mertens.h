@@ -111,10 +111,11 @@ int mertens_set_param(const char *key, double value);
  * mertens_stats -- counters of the last mertens_query, for benchmarking.
  * Writes up to cap doubles into vals in this order (returns how many):
  *   0 sieved y (Ymax+1)   1 blocks         2 u used        3 sum of L
- *   4 run-length pairs    5 explicit k pairs (pairs = (x, y) visits)
+ *   4 sum over x of Y (run-length range)  5 sum over x of explicit k terms
  *   6 ms sieve kernels    7 ms scan+fixup  8 ms update prep  9 ms update
  *  10 ms finalize         11 ms total device time          12 update launches
- *  13 sieve launches
+ *  13 sieve launches      14 run-length quotients taken (mu(y) != 0, y <= Y)
+ *  15 explicit k quotients taken (= M(y) gathers)
  * Kernel times are HIP-event intervals on the library's stream.
  */
 int mertens_stats(double *vals, int cap);

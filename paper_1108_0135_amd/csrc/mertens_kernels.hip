@@ -211,7 +211,8 @@ hipError_t launch_zero_u64(uint64_t *p, size_t n, hipStream_t s)
 // ====================================================================
 __global__ __launch_bounds__(UPD_THREADS) void k_plan(QueryArgs q)
 {
-    const uint32_t tile = blockIdx.x * (UPD_THREADS / 64) + (threadIdx.x >> 6);
+    const uint32_t tile =
+        __builtin_amdgcn_readfirstlane(blockIdx.x * (UPD_THREADS / 64) + (threadIdx.x >> 6));
     const uint32_t lane = lane_id();
     if (tile >= q.ntiles)
         return;
@@ -455,7 +456,8 @@ hipError_t launch_fixup(const BlockArgs &b, hipStream_t s)
 // work items of the run-length part and of the explicit k part.
 __global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockArgs b)
 {
-    const uint32_t tile = blockIdx.x * (UPD_THREADS / 64) + (threadIdx.x >> 6);
+    const uint32_t tile =
+        __builtin_amdgcn_readfirstlane(blockIdx.x * (UPD_THREADS / 64) + (threadIdx.x >> 6));
     const uint32_t lane = lane_id();
     if (blockIdx.x == 0 && threadIdx.x == 0)
         *q.counter = 0;
@@ -483,6 +485,9 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockA
             q.S[g] -= K * (uint64_t)M_at(b.masks, b.mb, Y - b.y1);
     }
     const bool has = klo <= khi;
+    const uint64_t kpairs = wave_sum_u64(has ? khi - klo + 1 : 0ull);
+    if (lane == 0 && kpairs)
+        atomicAdd((unsigned long long *)&q.pair_stats[3], (unsigned long long)kpairs);
     const uint64_t tmin = wave_min_u64(has ? klo : ~0ull);
     const uint64_t tmax = wave_max_u64(has ? khi : 0ull);
     const uint64_t mlen = wave_max_u64(has ? khi - klo + 1 : 0ull);
@@ -588,7 +593,7 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
         ce = yb_t;
     if (cs < y1e)
         cs = y1e;
-    uint64_t acc = 0;
+    uint64_t acc = 0, nq = 0;
     for (uint64_t wbase = cs & ~63ull; wbase <= ce; wbase += 64) {
         const uint64_t woff = (wbase - b.y1) >> 6;
         const uint64_t nz = uniform_u64(b.masks[2 * woff]);
@@ -598,6 +603,9 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
         uint64_t bits = nz & (~0ull << lob) & ((2ull << hib) - 1ull);
         if (bits == 0)
             continue;
+        // quotients this lane takes in this word (bits with y <= Y)
+        if (Y >= wbase)
+            nq += (Y - wbase >= 63) ? __popcll(bits) : __popcll(bits & ((2ull << (Y - wbase)) - 1ull));
         uint64_t mul;
         uint32_t sh1, sh2;
         gm_magic((uint32_t)(wbase + lane), mul, sh1, sh2);
@@ -619,6 +627,9 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
     }
     if (valid)
         atomicAdd((unsigned long long *)&q.S[g], (unsigned long long)acc);
+    nq = wave_sum_u64(nq);
+    if (lane == 0)
+        atomicAdd((unsigned long long *)&q.pair_stats[2], (unsigned long long)nq);
 }
 
 // Explicit k part of one (tile, k-chunk) item: S[x] += M(floor(m_x / k)) for
@@ -676,12 +687,15 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
 __global__ __launch_bounds__(UPD_THREADS) void k_update(QueryArgs q, BlockArgs b)
 {
     const uint32_t lane = lane_id();
-    const uint64_t total = q.tile_items[q.ntiles];
+    const uint64_t total = uniform_u64(q.tile_items[q.ntiles]);
     for (;;) {
-        uint32_t it = 0;
-        if (lane == 0)
-            it = atomicAdd(q.counter, 1u);
-        const uint64_t item = __shfl(it, 0, 64);
+        // One ticket per wave.  Every lane executes the atomic (lane 0 adds
+        // 1, the others 0) so the loop head holds no divergent branch, and
+        // readfirstlane turns the ticket into a scalar: the exit below is a
+        // uniform branch, and the compiler cannot split the wave across loop
+        // iterations around the cross-lane operations in the body.
+        const uint32_t it = atomicAdd(q.counter, lane == 0 ? 1u : 0u);
+        const uint64_t item = __builtin_amdgcn_readfirstlane(it);
         if (item >= total)
             break;
         const uint32_t tile =
@@ -715,7 +729,8 @@ __global__ __launch_bounds__(FIN_THREADS) void k_finalize(QueryArgs q)
     const uint64_t g0 = q.q_g0[qi];
     const uint64_t *S = q.S + g0;
     uint64_t *A = reinterpret_cast<uint64_t *>(q.A + g0);  // A[x-1], wrapping arithmetic
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     uint64_t xh = L;
     while (xh >= 1) {
         const uint64_t j = L / xh;

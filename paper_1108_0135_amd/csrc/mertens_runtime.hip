@@ -258,10 +258,13 @@ BlockArgs make_block(uint64_t y1, uint64_t y2)
     return b;
 }
 
-// Sieve one block: setup, sieve, segment scan, fixup.
-int sieve_block(const BlockArgs &b)
+// Sieve one block: residue setup, then the sieve kernel (an event may be
+// recorded between the two so the sieve kernel is timed alone).
+int sieve_block(const BlockArgs &b, hipEvent_t between = nullptr)
 {
     HIPCHK(launch_block_setup(b, g.stream));
+    if (between)
+        HIPCHK(hipEventRecord(between, g.stream));
     HIPCHK(launch_sieve(b, g.stream));
     return 0;
 }
@@ -421,7 +424,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
         return MERTENS_EIO;
     }
     HIPCHK(hipEventRecord(e_start, s));
-    HIPCHK(launch_zero_u64(g.pair_stats.as<uint64_t>(), 2, s));
+    HIPCHK(launch_zero_u64(g.pair_stats.as<uint64_t>(), 4, s));
     HIPCHK(launch_zero_u64(reinterpret_cast<uint64_t *>(g.carry.p), 1, s));
     HIPCHK(launch_plan(q, s));
     const uint32_t grid = (uint32_t)std::max(1, g.ncu * (int)g.waves_per_cu / (UPD_THREADS / 64));
@@ -439,8 +442,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
         }
         marks.push_back(ev);
         ev += 5;
-        HIPCHK(hipEventRecord(e0, s));
-        RCCHK(sieve_block(b));
+        RCCHK(sieve_block(b, e0));
         HIPCHK(hipEventRecord(e1, s));
         RCCHK(scan_block(b));
         HIPCHK(hipEventRecord(e2, s));
@@ -460,9 +462,9 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     HIPCHK(hipEventRecord(ef1, s));
     HIPCHK(launch_collect(q, g.out_dev.as<int64_t>(), s));
     res.resize(nq);
-    uint64_t pst[2] = {0, 0};
+    uint64_t pst[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(res.data(), g.out_dev.p, nq * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(pst, g.pair_stats.p, 16, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pst, g.pair_stats.p, 32, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
 
     double t_sieve = 0, t_scan = 0, t_prep = 0, t_upd = 0;
@@ -486,6 +488,8 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     g.stats[11] = elapsed(0, ev + 1);
     g.stats[12] = (double)nblocks;
     g.stats[13] = (double)nblocks;
+    g.stats[14] = (double)pst[2];
+    g.stats[15] = (double)pst[3];
     return 0;
 }
 
@@ -631,7 +635,7 @@ int mertens_stats(double *vals, int cap)
 {
     if (!vals || cap <= 0)
         return 0;
-    const int k = std::min(cap, 14);
+    const int k = std::min(cap, 16);
     for (int i = 0; i < k; ++i)
         vals[i] = g.stats[i];
     return k;

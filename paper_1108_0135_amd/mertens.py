@@ -18,9 +18,9 @@ HEADER_PATH = os.path.join(os.path.dirname(_PKG), "include", "mertens.h")
 
 EINVAL, ENOMEM, ENODEV, ERANGE, EIO, EAGAIN, EINPROGRESS = -22, -12, -19, -34, -5, -11, -115
 
-STAT_NAMES = ["sieved_y", "blocks", "u", "sum_L", "rl_pairs", "k_pairs", "ms_sieve",
+STAT_NAMES = ["sieved_y", "blocks", "u", "sum_L", "sum_Y", "sum_k", "ms_sieve",
               "ms_scan", "ms_prep", "ms_update", "ms_finalize", "ms_total", "update_launches",
-              "sieve_launches"]
+              "sieve_launches", "rl_quotients", "k_quotients"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1108_0135_amd.build`")
