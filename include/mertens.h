@@ -54,8 +54,8 @@ extern "C" {
  *          2^31 (else mertens_query returns MERTENS_EINVAL).
  *   block  y-block length of the sieve sweep (Section 3: y is processed in
  *          blocks, in increasing order).  0 = automatic (2^30, or less when
- *          the sweep is shorter).  Otherwise a multiple of 2^16 in
- *          [2^16, 2^31].
+ *          the sweep is shorter).  Otherwise a multiple of 2^17 in
+ *          [2^17, 2^31].
  * Returns 0, MERTENS_EINVAL (bad block), MERTENS_ENODEV, MERTENS_ENOMEM.
  * Calling it again frees the previous context first.
  */

@@ -8,17 +8,21 @@
 namespace mrt {
 
 // ---------------------------------------------------------------- constants
-// Sieve segment: one byte per y in LDS, processed by one workgroup.
-constexpr uint32_t SEG = 1u << 16;
+// Sieve segment: one byte per y in LDS (128 KB), processed by one workgroup.
+constexpr uint32_t SEG = 1u << 17;
 constexpr uint32_t SEG_WORDS = SEG / 64;     // 64-y mask words per segment
-constexpr int SIEVE_THREADS = 512;           // 8 waves, 2 mask words per thread
+constexpr int SIEVE_THREADS = 1024;          // 16 waves, 2 mask words per thread
 // Pre-sieved pattern: log sums of 2,3,5,7,11,13 and square flags of 4 and 9
 // repeat with period lcm(2,3,5,7,11,13,4,9) = 180180.
 constexpr uint32_t PAT = 180180;
 constexpr uint32_t PAT_WORDS = (PAT + SEG) / 4 + 16;
-// Sieving primes below this bound are walked by a whole wavefront (lane i
-// takes the i-th multiple); larger ones by one lane each.
-constexpr uint32_t SMALL_P = 1024;
+// Sieving primes below this bound (>= 64 multiples per segment) are walked by
+// a whole wavefront, lane i taking the i-th multiple; larger ones by one lane.
+constexpr uint32_t SMALL_P = SEG / 64;
+// Squares of primes up to this bound are flagged in LDS by whole wavefronts;
+// larger squares (at most 2^31 / 2^20 multiples per block each) are cleared
+// from the finished masks by a separate kernel.
+constexpr uint32_t SQ_LDS_P = 1024;
 // First index of the prime table that is sieved (table starts at 5; the
 // pattern covers 5, 7, 11, 13, so sieving starts at 17 = index 4).
 constexpr uint32_t FIRST_SIEVED = 4;
@@ -32,11 +36,10 @@ struct BlockArgs {
     uint32_t nseg;
     uint32_t n_small;   // primes with index in [FIRST_SIEVED, n_small) are < SMALL_P
     uint32_t n_sieve;   // primes with index < n_sieve are sieved (all p <= Psieve)
+    uint32_t n_sq_lds;  // primes with index < n_sq_lds have p <= SQ_LDS_P
     uint32_t n_sq;      // primes with index < n_sq have p^2 <= y2
     uint32_t pat_off;   // y1 mod PAT
-    const uint32_t *primes;   // primes >= 5, ascending
-    const uint8_t *logp;      // ceil(log2 p) | 1
-    uint32_t *res;            // y1 mod p      (per block)
+    uint2 *pres;              // {p, y1 mod p}: primes >= 5 ascending, residue per block
     uint64_t *res2;           // y1 mod p^2    (per block)
     const uint32_t *pat32;    // pattern bytes as words, length PAT_WORDS
     uint64_t *masks;          // per 64-y word: {squarefree bits, mu = -1 bits}
@@ -77,6 +80,8 @@ hipError_t launch_zero_u64(uint64_t *p, size_t n, hipStream_t s);
 hipError_t launch_plan(const QueryArgs &q, hipStream_t s);
 hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s);
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s);
+hipError_t launch_square_fix(const BlockArgs &b, hipStream_t s);
+hipError_t launch_scan_words(const BlockArgs &b, hipStream_t s);
 hipError_t launch_scan_segments(const BlockArgs &b, hipStream_t s);
 hipError_t launch_fixup(const BlockArgs &b, hipStream_t s);
 hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);

@@ -260,14 +260,20 @@ hipError_t launch_plan(const QueryArgs &q, hipStream_t s)
 // ====================================================================
 // a1: segmented Moebius block sieve (Section 3, modified algorithm).
 // ====================================================================
+// ceil(log2 p) | 1 for p >= 2
+__device__ inline uint32_t log_prime(uint32_t p)
+{
+    return (32u - (uint32_t)__clz((int)(p - 1u))) | 1u;
+}
+
 // Per block: residues of y1 modulo every sieving prime and square.
 __global__ void k_block_setup(BlockArgs b)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.n_sieve)
         return;
-    const uint64_t p = b.primes[i];
-    b.res[i] = (uint32_t)(b.y1 % p);
+    const uint64_t p = b.pres[i].x;
+    b.pres[i].y = (uint32_t)(b.y1 % p);
     if (i < b.n_sq)
         b.res2[i] = b.y1 % (p * p);
 }
@@ -289,14 +295,15 @@ hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s)
 //   A >= floor(log2 y) (fully split) -> mu = (-1)^A
 //   otherwise (one prime > Psieve)   -> mu = -(-1)^A
 // (A's parity is the number of sieving primes dividing y, as every l_p is
-// odd.)  The result is stored as two 64-bit masks per 64 y, plus exclusive
-// prefix sums of mu inside the segment.
+// odd.)  The result is stored as two 64-bit masks per 64 y.  Squares of
+// primes above SQ_LDS_P are cleared afterwards by k_square_fix.
 __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b)
 {
     __shared__ uint32_t lds[SEG / 4];
-    __shared__ int64_t wsum[SIEVE_THREADS / 64];
     const uint32_t seg = blockIdx.x;
-    const uint32_t tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    constexpr uint32_t NWAVES = SIEVE_THREADS / 64;
     const uint32_t segbase = seg * SEG;  // < 2^31
     const uint64_t s0 = b.y1 + segbase;
 
@@ -309,45 +316,55 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b)
         lds[j] = src[j];
     __syncthreads();
 
+    // squares p^2 <= SQ_LDS_P^2: one wave per prime, lane i takes multiple i
+    for (uint32_t i = wave; i < b.n_sq_lds; i += NWAVES) {
+        const uint32_t p = b.pres[i].x;
+        const uint32_t p2 = p * p;  // < 2^21
+        uint32_t r = (uint32_t)b.res2[i] + segbase % p2;
+        if (r >= p2)
+            r -= p2;
+        const uint32_t first = r ? p2 - r : 0;
+        for (uint32_t o = first + lane * p2; o < SEG; o += 64 * p2)
+            atomicOr(&lds[o >> 2], 0x80u << ((o & 3u) << 3));
+    }
     // small primes: one wave per prime, lane i takes multiples i, i+64, ...
-    for (uint32_t i = FIRST_SIEVED + wave; i < b.n_small; i += SIEVE_THREADS / 64) {
-        const uint32_t p = b.primes[i];
-        const uint32_t lp = b.logp[i];
-        uint32_t r = b.res[i] + segbase % p;  // both < p < 2^10
+    for (uint32_t i = FIRST_SIEVED + wave; i < b.n_small; i += NWAVES) {
+        const uint2 e = b.pres[i];
+        const uint32_t p = e.x, lp = log_prime(p);
+        uint32_t r = e.y + segbase % p;  // both < p < SMALL_P
         if (r >= p)
             r -= p;
         const uint32_t first = r ? p - r : 0;
         for (uint32_t o = first + lane * p; o < SEG; o += 64 * p)
             atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
     }
-    // larger primes: one lane per prime
-    for (uint32_t i = (b.n_small > FIRST_SIEVED ? b.n_small : FIRST_SIEVED) + tid; i < b.n_sieve;
-         i += SIEVE_THREADS) {
-        const uint32_t p = b.primes[i];
-        const uint32_t lp = b.logp[i];
-        uint64_t r = (uint64_t)b.res[i] + segbase % p;
-        if (r >= p)
-            r -= p;
-        const uint64_t first = r ? p - r : 0;
-        for (uint64_t o = first; o < SEG; o += p)
-            atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
-    }
-    // squares of primes >= 5
-    for (uint32_t i = tid; i < b.n_sq; i += SIEVE_THREADS) {
-        const uint64_t p = b.primes[i];
-        const uint64_t p2 = p * p;
-        uint64_t r = b.res2[i] + (p2 <= 0x80000000ull ? (uint64_t)(segbase % (uint32_t)p2)
-                                                       : (uint64_t)segbase);
-        if (r >= p2)
-            r -= p2;
-        const uint64_t first = r ? p2 - r : 0;
-        for (uint64_t o = first; o < SEG; o += p2)
-            atomicOr(&lds[o >> 2], 0x80u << ((o & 3u) << 3));
+    // larger primes (at most SEG/SMALL_P = 64 multiples): one lane per prime,
+    // four primes' table entries loaded ahead of their walks
+    const uint32_t i0 = (b.n_small > FIRST_SIEVED ? b.n_small : FIRST_SIEVED) + tid;
+    for (uint32_t i = i0; i < b.n_sieve; i += 4 * SIEVE_THREADS) {
+        uint2 e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t k = i + (uint32_t)u * SIEVE_THREADS;
+            e[u] = k < b.n_sieve ? b.pres[k] : make_uint2(0u, 0u);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint32_t p = e[u].x;
+            if (p == 0)
+                continue;
+            const uint32_t lp = log_prime(p);
+            uint64_t r = (uint64_t)e[u].y + segbase % p;
+            if (r >= p)
+                r -= p;
+            const uint64_t first = r ? p - r : 0;
+            for (uint64_t o = first; o < SEG; o += p)
+                atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
+        }
     }
     __syncthreads();
 
     // classify: thread t owns words t and t + SIEVE_THREADS of the segment
-    int64_t cnt[2];
     for (int h = 0; h < 2; ++h) {
         const uint32_t w = tid + (uint32_t)h * SIEVE_THREADS;
         const uint64_t ybase = s0 + (uint64_t)w * 64;
@@ -382,21 +399,66 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b)
         const uint64_t gw = (uint64_t)seg * SEG_WORDS + w;
         b.masks[2 * gw] = nz;
         b.masks[2 * gw + 1] = ng;
-        cnt[h] = (int64_t)__popcll(nz) - 2 * (int64_t)__popcll(ng);
     }
-    int64_t tot0, tot1;
-    const int64_t ex0 = wg_exclusive_scan<SIEVE_THREADS>(cnt[0], wsum, tot0);
-    const int64_t ex1 = wg_exclusive_scan<SIEVE_THREADS>(cnt[1], wsum, tot1);
-    const uint64_t gw0 = (uint64_t)seg * SEG_WORDS + tid;
-    b.mb[gw0] = ex0;
-    b.mb[gw0 + SIEVE_THREADS] = tot0 + ex1;
-    if (tid == 0)
-        b.seg_sum[seg] = (int32_t)(tot0 + tot1);
 }
 
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s)
 {
     hipLaunchKernelGGL(k_sieve, dim3(b.nseg), dim3(SIEVE_THREADS), 0, s, b);
+    return hipGetLastError();
+}
+
+// Squares p^2 of primes p > SQ_LDS_P with p^2 <= y2: clear their multiples in
+// [y1, y2] from both masks (mu = 0).  One thread per prime; at most
+// B / 2^20 multiples each.
+__global__ void k_square_fix(BlockArgs b)
+{
+    const uint32_t i = b.n_sq_lds + blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= b.n_sq)
+        return;
+    const uint64_t p = b.pres[i].x;
+    const uint64_t p2 = p * p;
+    const uint64_t r = b.res2[i];
+    const uint64_t span = b.y2 - b.y1;
+    for (uint64_t o = r ? p2 - r : 0; o <= span; o += p2) {
+        const uint64_t w = o >> 6;
+        const unsigned long long keep = ~(1ull << (o & 63));
+        atomicAnd((unsigned long long *)&b.masks[2 * w], keep);
+        atomicAnd((unsigned long long *)&b.masks[2 * w + 1], keep);
+    }
+}
+
+hipError_t launch_square_fix(const BlockArgs &b, hipStream_t s)
+{
+    if (b.n_sq <= b.n_sq_lds)
+        return hipSuccess;
+    const uint32_t n = b.n_sq - b.n_sq_lds;
+    hipLaunchKernelGGL(k_square_fix, dim3((n + 255) / 256), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+// Per segment: exclusive prefix sums of mu over its mask words (mb, local to
+// the segment) and the segment's total.
+__global__ __launch_bounds__(SIEVE_THREADS) void k_scan_words(BlockArgs b)
+{
+    __shared__ int64_t wsum[SIEVE_THREADS / 64];
+    const uint32_t seg = blockIdx.x, tid = threadIdx.x;
+    const uint64_t gw0 = (uint64_t)seg * SEG_WORDS + tid;
+    const uint64_t gw1 = gw0 + SIEVE_THREADS;
+    const int64_t c0 = (int64_t)__popcll(b.masks[2 * gw0]) - 2 * (int64_t)__popcll(b.masks[2 * gw0 + 1]);
+    const int64_t c1 = (int64_t)__popcll(b.masks[2 * gw1]) - 2 * (int64_t)__popcll(b.masks[2 * gw1 + 1]);
+    int64_t tot0, tot1;
+    const int64_t ex0 = wg_exclusive_scan<SIEVE_THREADS>(c0, wsum, tot0);
+    const int64_t ex1 = wg_exclusive_scan<SIEVE_THREADS>(c1, wsum, tot1);
+    b.mb[gw0] = ex0;
+    b.mb[gw1] = tot0 + ex1;
+    if (tid == 0)
+        b.seg_sum[seg] = (int32_t)(tot0 + tot1);
+}
+
+hipError_t launch_scan_words(const BlockArgs &b, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_scan_words, dim3(b.nseg), dim3(SIEVE_THREADS), 0, s, b);
     return hipGetLastError();
 }
 

@@ -96,7 +96,7 @@ uint64_t ceil_sqrt_host(uint64_t v)
     return (r * r < v) ? r + 1 : r;
 }
 
-uint8_t log_prime(uint64_t p)
+uint8_t log_prime_host(uint64_t p)
 {
     uint32_t l = 0;
     while ((1ull << l) < p)
@@ -117,7 +117,7 @@ struct Ctx {
     // sieving primes (>= 5) up to psieve, and the pre-sieved pattern
     uint64_t psieve = 0;
     std::vector<uint32_t> h_primes;
-    DevBuf primes, logp, res, res2, pattern;
+    DevBuf pres, res2, pattern;
     // block buffers
     DevBuf masks, mb, seg_sum, seg_off, carry;
     // query buffers
@@ -135,7 +135,7 @@ Ctx g;
 
 void free_all()
 {
-    DevBuf *bufs[] = {&g.primes, &g.logp, &g.res, &g.res2, &g.pattern, &g.masks, &g.mb,
+    DevBuf *bufs[] = {&g.pres, &g.res2, &g.pattern, &g.masks, &g.mb,
                       &g.seg_sum, &g.seg_off, &g.carry, &g.q_n, &g.q_L, &g.q_g0, &g.x_m,
                       &g.x_Y, &g.x_K, &g.x_k0, &g.S, &g.A, &g.x_klo, &g.x_khi, &g.tile_q,
                       &g.tile_x0, &g.tile_nx, &g.tile_g0, &g.tile_ymax, &g.tile_klo,
@@ -158,8 +158,8 @@ void free_all()
     g.ready = false;
 }
 
-// Sieving primes p in [5, limit] (plain Eratosthenes on odd numbers), their
-// log-primes, and device copies.  Grows only.
+// Sieving primes p in [5, limit] (plain Eratosthenes on odd numbers) and
+// their device copy as {p, residue} pairs.  Grows only.
 int ensure_primes(uint64_t limit)
 {
     if (limit <= g.psieve)
@@ -169,20 +169,17 @@ int ensure_primes(uint64_t limit)
         if (!comp[i / 2])
             for (uint64_t j = i * i; j <= limit; j += 2 * i)
                 comp[j / 2] = 1;
-    std::vector<uint32_t> pr;
-    std::vector<uint8_t> lp;
+    std::vector<uint32_t> pr, pairs;
     for (uint64_t v = 5; v <= limit; v += 2)
         if (!comp[v / 2]) {
             pr.push_back((uint32_t)v);
-            lp.push_back(log_prime(v));
+            pairs.push_back((uint32_t)v);
+            pairs.push_back(0u);
         }
     const size_t np = pr.size();
-    RCCHK(ensure(g.primes, np * 4));
-    RCCHK(ensure(g.logp, np));
-    RCCHK(ensure(g.res, np * 4));
+    RCCHK(ensure(g.pres, np * 8));
     RCCHK(ensure(g.res2, np * 8));
-    HIPCHK(hipMemcpy(g.primes.p, pr.data(), np * 4, hipMemcpyHostToDevice));
-    HIPCHK(hipMemcpy(g.logp.p, lp.data(), np, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(g.pres.p, pairs.data(), np * 8, hipMemcpyHostToDevice));
     g.h_primes.swap(pr);
     g.psieve = limit;
     return 0;
@@ -200,7 +197,7 @@ int upload_pattern()
         uint32_t a = 0;
         for (uint32_t p : small)
             if (r % p == 0)
-                a += log_prime(p);
+                a += log_prime_host(p);
         if (r % 4 == 0 || r % 9 == 0)
             a |= 0x80u;
         pat[i] = (uint8_t)a;
@@ -244,10 +241,9 @@ BlockArgs make_block(uint64_t y1, uint64_t y2)
     b.n_small = count_primes_upto(SMALL_P - 1);
     b.n_sieve = (uint32_t)g.h_primes.size();
     b.n_sq = count_squares_upto(y2);
+    b.n_sq_lds = std::min(count_primes_upto(SQ_LDS_P), b.n_sq);
     b.pat_off = (uint32_t)(y1 % PAT);
-    b.primes = g.primes.as<uint32_t>();
-    b.logp = g.logp.as<uint8_t>();
-    b.res = g.res.as<uint32_t>();
+    b.pres = g.pres.as<uint2>();
     b.res2 = g.res2.as<uint64_t>();
     b.pat32 = g.pattern.as<uint32_t>();
     b.masks = g.masks.as<uint64_t>();
@@ -266,11 +262,13 @@ int sieve_block(const BlockArgs &b, hipEvent_t between = nullptr)
     if (between)
         HIPCHK(hipEventRecord(between, g.stream));
     HIPCHK(launch_sieve(b, g.stream));
+    HIPCHK(launch_square_fix(b, g.stream));
     return 0;
 }
 
 int scan_block(const BlockArgs &b)
 {
+    HIPCHK(launch_scan_words(b, g.stream));
     HIPCHK(launch_scan_segments(b, g.stream));
     HIPCHK(launch_fixup(b, g.stream));
     return 0;
@@ -503,7 +501,7 @@ extern "C" {
 int mertens_init(uint64_t u, uint64_t block)
 {
     if (block != 0 && (block < SEG || block % SEG != 0 || block > (1ull << 31))) {
-        set_error_text("block must be 0 or a multiple of 65536 in [65536, 2^31]");
+        set_error_text("block must be 0 or a multiple of 131072 in [131072, 2^31]");
         return MERTENS_EINVAL;
     }
     if (g.ready)

@@ -30,7 +30,7 @@ def test_strerror_codes():
 def test_bad_arguments_without_gpu():
     lib = mt.raw()
     # invalid block sizes are rejected before any device call
-    for blk in (1, 65535, 65536 + 64, (1 << 31) + 65536):
+    for blk in (1, 65536, 131072 + 64, (1 << 31) + 131072):
         assert lib.mertens_init(0, blk) == mt.EINVAL
     # count 0 touches nothing; null pointers with count > 0 are rejected
     assert lib.mertens_query(None, 0, None) == 0

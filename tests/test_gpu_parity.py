@@ -78,7 +78,7 @@ def test_small_n_every_value(mt):
 
 @pytest.mark.parametrize("u", [2, 7, 100, 10**4])
 def test_small_n_fixed_u(mt, u):
-    _reinit(mt, u=u, block=1 << 16)
+    _reinit(mt, u=u, block=1 << 17)
     ns = np.arange(1, 2001, dtype=np.uint64)
     assert np.array_equal(mt.query(ns), oracle.mertens_table(2000)[1:].astype(np.int64))
 
@@ -107,7 +107,7 @@ def test_n1e12_and_byproducts(mt):
 
 
 @pytest.mark.parametrize("u,block,params", [
-    (10**8, 1 << 16, {}),
+    (10**8, 1 << 17, {}),
     (3 * 10**7, 1 << 20, {"beta": 1.0}),
     (2 * 10**8, 1 << 24, {"beta": 0.25, "ychunk": 64, "kchunk": 64}),
     (10**8, 1 << 26, {"ychunk": 1 << 16, "kchunk": 1 << 15, "klchunk": 1}),
