@@ -99,7 +99,7 @@ int mertens_set_stream(void *hip_stream);
  * mertens_set_param -- tuning knobs (results never depend on them).
  *   "beta"        split of the per-x sum between the run-length part over
  *                 y <= Y and the explicit k part (K = floor(beta*sqrt(m))),
- *                 in (0, 1]; default 0.5
+ *                 in (0, 1]; default 0.2
  *   "ychunk"      y per work item of the run-length part, multiple of 64
  *   "kchunk"      k per work item of the explicit k part
  *   "waves_per_cu" persistent update grid size per compute unit

@@ -632,11 +632,37 @@ __device__ inline uint32_t find_tile(const uint64_t *__restrict__ prefix, uint32
     return lo;
 }
 
+// Exact quotients through fp64.  For m < 2^64 and 1 <= d < 2^32 with
+// floor(m/d) < 2^32, the product (double)m * (1.0/d) carries three
+// roundings of relative size 2^-53, so it lies within 2^-19.4 of m/d.
+// When its fractional part is at least QEPS = 2^-19 away from an integer,
+// its truncation is the exact floor; otherwise (rare) the lane recomputes
+// the remainder in integers and corrects by one.
+constexpr double QEPS = 1.0 / 524288.0;
+
+__device__ inline double readlane_f64(double v, uint32_t lane)
+{
+    return __longlong_as_double((long long)readlane_u64((uint64_t)__double_as_longlong(v), lane));
+}
+
+// exact floor(m/d) from the truncated estimate t (|t - m/d| < 1)
+__device__ inline uint64_t fix_quotient(uint64_t m, uint64_t d, double t)
+{
+    uint64_t qv = (uint64_t)t;
+    const int64_t r = (int64_t)(m - qv * d);
+    if (r < 0)
+        qv -= 1;
+    else if ((uint64_t)r >= d)
+        qv += 1;
+    return qv;
+}
+
 // Run-length part of one (tile, y-chunk) item:
 //   S[x] += sum_{y in chunk, y <= Y_x, mu(y) != 0} mu(y) floor(m_x / y).
 // y is uniform across the wave (lane = x): the mask words come from scalar
-// loads, the 64 divisor constants of a word are computed one per lane and
-// broadcast with readlane.
+// loads, and per 64-y word each lane computes one divisor's constants (1/y
+// for the fp64 path, the Granlund-Montgomery multiplier for the integer
+// path), which readlane broadcasts.
 __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t tile, uint64_t c)
 {
     const uint32_t lane = lane_id();
@@ -645,6 +671,12 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
     const bool valid = lane < nx;
     const uint64_t m = valid ? q.x_m[g] : 0;
     const uint64_t Y = valid ? q.x_Y[g] : 0;
+    // m as fp64; NaN on lanes past the tile's end, so their near-integer
+    // test below never fires (they never write S)
+    const double mfq = valid ? (double)m : __longlong_as_double(0x7ff8000000000000ll);
+    // lane 0 holds the tile's smallest x, hence its largest m
+    const uint64_t qbig = uniform_u64(m) >> 32;  // y > qbig => every quotient < 2^32
+    const uint64_t ymin = uniform_u64(wave_min_u64(valid ? Y : ~0ull));
     const uint64_t y1e = b.y1 > 0 ? b.y1 : 1;
     const uint64_t tymax = uniform_u64(q.tile_ymax[tile]);
     const uint64_t yb_t = tymax < b.y2 ? tymax : b.y2;
@@ -656,6 +688,7 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
     if (cs < y1e)
         cs = y1e;
     uint64_t acc = 0, nq = 0;
+    double accf = 0.0;  // integer-valued, |accf| < ychunk * 2^32 < 2^53
     for (uint64_t wbase = cs & ~63ull; wbase <= ce; wbase += 64) {
         const uint64_t woff = (wbase - b.y1) >> 6;
         const uint64_t nz = uniform_u64(b.masks[2 * woff]);
@@ -668,30 +701,88 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
         // quotients this lane takes in this word (bits with y <= Y)
         if (Y >= wbase)
             nq += (Y - wbase >= 63) ? __popcll(bits) : __popcll(bits & ((2ull << (Y - wbase)) - 1ull));
-        uint64_t mul;
-        uint32_t sh1, sh2;
-        gm_magic((uint32_t)(wbase + lane), mul, sh1, sh2);
-        while (bits) {
-            const uint32_t bt = (uint32_t)__builtin_ctzll(bits);
-            bits &= bits - 1;
-            const uint64_t y = wbase + bt;
-            const uint64_t mg = readlane_u64(mul, bt);
-            const uint32_t s1 = __builtin_amdgcn_readlane(sh1, bt);
-            const uint32_t s2 = __builtin_amdgcn_readlane(sh2, bt);
-            const uint64_t qv = gm_div(m, mg, s1, s2);
-            if (y <= Y) {
-                if ((ng >> bt) & 1ull)
-                    acc -= qv;
-                else
-                    acc += qv;
+        if (wbase > qbig) {
+            const double rl = 1.0 / (double)(wbase + lane);
+            if (wbase + 63 <= ymin) {
+                // every lane takes every y of the word; mu = +1 bits, then -1
+                uint64_t pos = bits & ~ng, neg = bits & ng;
+                while (pos) {
+                    const uint32_t bt = (uint32_t)__builtin_ctzll(pos);
+                    pos &= pos - 1;
+                    const double qd = mfq * readlane_f64(rl, bt);
+                    const double t = trunc(qd);
+                    accf += t;
+                    if (fabs(qd - t - 0.5) > 0.5 - QEPS)
+                        accf += (double)(int64_t)(fix_quotient(m, wbase + bt, t) - (uint64_t)t);
+                }
+                while (neg) {
+                    const uint32_t bt = (uint32_t)__builtin_ctzll(neg);
+                    neg &= neg - 1;
+                    const double qd = mfq * readlane_f64(rl, bt);
+                    const double t = trunc(qd);
+                    accf -= t;
+                    if (fabs(qd - t - 0.5) > 0.5 - QEPS)
+                        accf -= (double)(int64_t)(fix_quotient(m, wbase + bt, t) - (uint64_t)t);
+                }
+            } else {
+                while (bits) {
+                    const uint32_t bt = (uint32_t)__builtin_ctzll(bits);
+                    bits &= bits - 1;
+                    const uint64_t y = wbase + bt;
+                    const double qd = mfq * readlane_f64(rl, bt);
+                    if (y <= Y) {
+                        double t = trunc(qd);
+                        if (fabs(qd - t - 0.5) > 0.5 - QEPS)
+                            t = (double)fix_quotient(m, y, t);
+                        accf += ((ng >> bt) & 1ull) ? -t : t;
+                    }
+                }
+            }
+        } else {
+            // quotients may reach 2^32: Granlund-Montgomery integer path
+            uint64_t mul;
+            uint32_t sh1, sh2;
+            gm_magic((uint32_t)(wbase + lane), mul, sh1, sh2);
+            while (bits) {
+                const uint32_t bt = (uint32_t)__builtin_ctzll(bits);
+                bits &= bits - 1;
+                const uint64_t y = wbase + bt;
+                const uint64_t mg = readlane_u64(mul, bt);
+                const uint32_t s1 = __builtin_amdgcn_readlane(sh1, bt);
+                const uint32_t s2 = __builtin_amdgcn_readlane(sh2, bt);
+                const uint64_t qv = gm_div(m, mg, s1, s2);
+                if (y <= Y) {
+                    if ((ng >> bt) & 1ull)
+                        acc -= qv;
+                    else
+                        acc += qv;
+                }
             }
         }
     }
+    acc += (uint64_t)(int64_t)accf;
     if (valid)
         atomicAdd((unsigned long long *)&q.S[g], (unsigned long long)acc);
     nq = wave_sum_u64(nq);
     if (lane == 0)
         atomicAdd((unsigned long long *)&q.pair_stats[2], (unsigned long long)nq);
+}
+
+// exact floor(m / k) for any k >= 1 from an fp64 estimate and integer
+// correction steps (one step suffices while the quotient is below 2^50)
+__device__ inline uint64_t div_fp_exact(uint64_t m, uint64_t k)
+{
+    uint64_t qv = (uint64_t)((double)m / (double)k);
+    int64_t r = (int64_t)(m - qv * k);
+    while (r < 0) {
+        qv -= 1;
+        r += (int64_t)k;
+    }
+    while ((uint64_t)r >= k) {
+        qv += 1;
+        r -= (int64_t)k;
+    }
+    return qv;
 }
 
 // Explicit k part of one (tile, k-chunk) item: S[x] += M(floor(m_x / k)) for
@@ -708,24 +799,42 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
     uint64_t acc = 0;
     if (__builtin_amdgcn_readfirstlane(q.tile_mode[tile]) == 0) {
         // uniform k across the wave
+        const double mf = (double)m;
+        const uint64_t qbig = uniform_u64(m) >> 32;  // k > qbig => quotients < 2^32
         const uint64_t kb = uniform_u64(q.tile_klo[tile]) + c * q.kchunk;
         const uint64_t tkhi = uniform_u64(q.tile_khi[tile]);
         uint64_t ke = kb + q.kchunk - 1;
         if (ke > tkhi)
             ke = tkhi;
         for (uint64_t kk = kb; kk <= ke; kk += 64) {
-            uint64_t mul;
-            uint32_t sh1, sh2;
-            gm_magic((uint32_t)(kk + lane), mul, sh1, sh2);
             const uint32_t jmax = (ke - kk) < 63 ? (uint32_t)(ke - kk) : 63u;
-            for (uint32_t j = 0; j <= jmax; ++j) {
-                const uint64_t k = kk + j;
-                const uint64_t mg = readlane_u64(mul, j);
-                const uint32_t s1 = __builtin_amdgcn_readlane(sh1, j);
-                const uint32_t s2 = __builtin_amdgcn_readlane(sh2, j);
-                if (k >= klo && k <= khi) {
-                    const uint64_t y = gm_div(m, mg, s1, s2);
-                    acc += (uint64_t)M_at(b.masks, b.mb, y - b.y1);
+            if (kk > qbig) {
+                const double rl = 1.0 / (double)(kk + lane);
+                for (uint32_t j = 0; j <= jmax; ++j) {
+                    const uint64_t k = kk + j;
+                    const double qd = mf * readlane_f64(rl, j);
+                    if (k >= klo && k <= khi) {
+                        const double t = trunc(qd);
+                        // t < 2^32 unless the near-integer test fires
+                        uint64_t y = (uint32_t)t;
+                        if (fabs(qd - t - 0.5) > 0.5 - QEPS)
+                            y = fix_quotient(m, k, t);
+                        acc += (uint64_t)M_at(b.masks, b.mb, y - b.y1);
+                    }
+                }
+            } else {
+                uint64_t mul;
+                uint32_t sh1, sh2;
+                gm_magic((uint32_t)(kk + lane), mul, sh1, sh2);
+                for (uint32_t j = 0; j <= jmax; ++j) {
+                    const uint64_t k = kk + j;
+                    const uint64_t mg = readlane_u64(mul, j);
+                    const uint32_t s1 = __builtin_amdgcn_readlane(sh1, j);
+                    const uint32_t s2 = __builtin_amdgcn_readlane(sh2, j);
+                    if (k >= klo && k <= khi) {
+                        const uint64_t y = gm_div(m, mg, s1, s2);
+                        acc += (uint64_t)M_at(b.masks, b.mb, y - b.y1);
+                    }
                 }
             }
         }
@@ -736,7 +845,7 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
         if (ke > khi)
             ke = khi;
         for (uint64_t k = ks; k <= ke && klo <= khi; ++k) {
-            const uint64_t y = m / k;
+            const uint64_t y = div_fp_exact(m, k);
             acc += (uint64_t)M_at(b.masks, b.mb, y - b.y1);
         }
     }
@@ -757,7 +866,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(QueryArgs q, BlockArgs b
         // uniform branch, and the compiler cannot split the wave across loop
         // iterations around the cross-lane operations in the body.
         const uint32_t it = atomicAdd(q.counter, lane == 0 ? 1u : 0u);
-        const uint64_t item = __builtin_amdgcn_readfirstlane(it);
+        const uint64_t item = (uint32_t)__builtin_amdgcn_readfirstlane(it);
         if (item >= total)
             break;
         const uint32_t tile =

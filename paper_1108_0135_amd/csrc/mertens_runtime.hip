@@ -112,8 +112,8 @@ struct Ctx {
     hipStream_t stream = nullptr;
     uint64_t u_req = 0, block_req = 0;
     // tuning
-    double beta = 0.5;
-    uint32_t ychunk = 8192, kchunk = 4096, klchunk = 256, waves_per_cu = 16;
+    double beta = 0.2;
+    uint32_t ychunk = 4096, kchunk = 2048, klchunk = 256, waves_per_cu = 16;
     // sieving primes (>= 5) up to psieve, and the pre-sieved pattern
     uint64_t psieve = 0;
     std::vector<uint32_t> h_primes;

@@ -149,3 +149,27 @@ def test_table1_1e16(mt):
     assert [int(byp[c - 1]) for c in g["c"]] == g["M"]
     st = mt.stats()
     assert st["blocks"] == 47 and st["sieved_y"] == 10**16 // (2 * 10**5 + 1) + 1
+
+
+@pytest.mark.parametrize("n", [10**17, 10**18])
+def test_table1_large(mt, n):
+    # Table 1 of the paper at the automatic u = n^(2/3)
+    _reinit(mt)
+    assert int(mt.query([n])[0]) == inputs.TABLE1[n]
+
+
+def test_table1_1e19_and_byproduct_chain(mt):
+    # Table 1: M(10^19); its byproducts at c = 10, 100, 1000 are M(10^18), M(10^17), M(10^16)
+    # (Section 5 checks byproducts of one run against direct runs the same way)
+    _reinit(mt)
+    assert int(mt.query([10**19])[0]) == inputs.TABLE1[10**19]
+    byp = mt.byproducts(0)
+    assert [int(byp[c - 1]) for c in (10, 100, 1000)] == [inputs.TABLE1[10**18],
+                                                          inputs.TABLE1[10**17],
+                                                          inputs.TABLE1[10**16]]
+
+
+def test_section6_extreme(mt):
+    # Section 6: M(11609864264058592345) = -1,995,900,927
+    _reinit(mt)
+    assert int(mt.query([inputs.EXTREME_N])[0]) == inputs.EXTREME_M
