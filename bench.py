@@ -1,16 +1,20 @@
 """Benchmark: exact M(n) on one MI355X through the HIP C ABI.
 
-A step is one full pass of the hot path for the workload n = 10^16 with
-u = 5*10^10 and y-blocks of 2^30 (47 blocks, L = 2*10^5 byproducts):
-block sieve -> M(y) prefix scan -> per-block contribution update ->
-finalize.  The metric is sieved y per second through the update (the
-sweep covers y in [0, floor(n/(L+1))]); the step's result is checked
-against Table 1 of the paper before timing.
+Default workload (the one line the contract asks for): a step is one full
+pass of the hot path for n = 10^16 with u = 5*10^10 and y-blocks of 2^30
+(47 blocks, L = 2*10^5 byproducts): block sieve -> M(y) prefix scan ->
+per-block contribution update -> finalize.  The metric is sieved y per
+second through the update (the sweep covers y in [0, floor(n/(L+1))]);
+every step's result is checked against Table 1 of the paper.  The line also
+carries a small batched-vs-plain comparison, the roofline of the dominant
+kernel (HIP events on the library stream) and the CPU oracle's rate.
 
-Prints ONE JSON line (see the repository's benchmark contract).  The
-`roofline` object is for the dominant kernel, timed with HIP events on the
-library's own stream; `cpu_baseline` times the CPU oracle on a bounded
-sample on this host.
+Other workloads (``--workload``), reported separately:
+  batched  256 n log-uniform in [1e13, 1e17] (seed 0) plus 1e16 and 1e17,
+           one shared sweep vs. one query at a time
+  serving  Poisson arrivals (``--rate`` q/s, ``--count`` queries, n
+           log-uniform in [1e10, 1e18]) through mertens_submit/poll vs. a
+           one-at-a-time FIFO server; p50/p99 latency and queries/s
 """
 from __future__ import annotations
 
@@ -27,14 +31,14 @@ N_WORK = 10**16
 U_WORK = 5 * 10**10
 BLOCK_WORK = 1 << 30
 EXPECTED = -3195437  # Table 1 of the paper
+METRIC = "sieved y/sec through update; batched vs plain M(n) queries/sec, 1 GPU, exact"
 
-# MI355X published peaks used for the roofline
+# MI355X published figures used for the roofline
 HBM_PEAK_GBS = 8000.0
 CU, CLOCK_GHZ, LANES = 256, 2.4, 64
 INT_VALU_PEAK_TOPS = CU * LANES * CLOCK_GHZ / 1000.0  # 39.3 T int32 lane-ops/s
 # algorithmic cost of one quotient floor(m/d) by an invariant divisor plus its
-# accumulation, in full-rate int32 lane-op equivalents: 4 32x32->64 products
-# (quarter rate, 4 slots each) + 8 add/sub/shift ops
+# accumulation, in full-rate int32 lane-op equivalents
 OPS_PER_QUOTIENT = 24
 
 
@@ -59,28 +63,32 @@ def cpu_baseline(budget_s: float = 15.0) -> dict:
                       f"M(1e16) would need the whole [1, 1e16] sieved"}
 
 
-def main() -> int:
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(see DESIGN.md for how the sweep would shard)", file=sys.stderr)
-        return 2
+def batched_vs_plain(mt, ns) -> dict:
+    """queries/s of one shared sweep vs. the same queries one at a time."""
+    mt.init(0, 0)
+    mt.query(ns[:2])  # warm
+    t0 = time.perf_counter()
+    plain = [int(mt.query([n])[0]) for n in ns]
+    t_plain = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batched = [int(v) for v in mt.query(ns)]
+    t_batch = time.perf_counter() - t0
+    if batched != plain:
+        raise RuntimeError("batched results differ from one-at-a-time results")
+    st = mt.stats()
+    return {"queries": len(ns), "plain_qps": len(ns) / t_plain, "batched_qps": len(ns) / t_batch,
+            "speedup": t_plain / t_batch, "plain_s": t_plain, "batched_s": t_batch,
+            "batched_u": st["u"], "batched_sieved_y": st["sieved_y"]}
 
+
+def workload_default(args, mt) -> dict:
     import torch
-    from paper_1108_0135_amd import mertens as mt
 
     mt.init(U_WORK, BLOCK_WORK)
     for _ in range(max(args.warmup, 1)):
         got = int(mt.query([N_WORK])[0])
         if got != EXPECTED:
-            print(f"wrong result M(1e16) = {got}, expected {EXPECTED}", file=sys.stderr)
-            return 1
-
+            raise RuntimeError(f"wrong result M(1e16) = {got}, expected {EXPECTED}")
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     kstats = []
@@ -88,8 +96,7 @@ def main() -> int:
         r = int(mt.query([N_WORK])[0])
         kstats.append(mt.stats())
         if r != EXPECTED:
-            print(f"wrong result in timed step: {r}", file=sys.stderr)
-            return 1
+            raise RuntimeError(f"wrong result in timed step: {r}")
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_step = 1000.0 * dt / args.steps
@@ -104,7 +111,7 @@ def main() -> int:
     sieve_ms_launch = avg("ms_sieve") / st["sieve_launches"]
     quot = st["rl_quotients"] + st["k_quotients"]
     upd_tops = quot / launches * OPS_PER_QUOTIENT / (upd_ms_launch * 1e-3) / 1e12
-    # sieve kernel: HBM bytes it must write per y (two 64-bit masks per 64 y)
+    # sieve kernels: HBM bytes they must write per y (two 64-bit masks per 64 y)
     sieve_gbs = (sieved / st["sieve_launches"]) * 0.25 / (sieve_ms_launch * 1e-3) / 1e9
     if avg("ms_update") >= avg("ms_sieve"):
         roof = {"kernel": "k_update", "bound": "alu", "achieved": upd_tops,
@@ -117,9 +124,8 @@ def main() -> int:
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sieve_gbs / HBM_PEAK_GBS,
                 "traffic": None, "avg_launch_ms": sieve_ms_launch,
                 "launches": st["sieve_launches"]}
-
     line = {
-        "metric": "sieved y/sec through update; batched vs plain M(n) queries/sec, 1 GPU, exact",
+        "metric": METRIC,
         "value": sieved / (ms_step * 1e-3),
         "unit": "sieved y/s",
         "n_gpus": 1,
@@ -141,9 +147,114 @@ def main() -> int:
         "quotients": {"run_length": st["rl_quotients"], "explicit_k": st["k_quotients"]},
         "roofline": roof,
     }
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline()
+    if not args.no_batched:
+        from paper_1108_0135_amd import inputs
+        ns = [int(v) for v in inputs.batch_log_uniform(seed=0, count=16, lo=1e13, hi=1e15)]
+        line["batched_sample"] = dict(batched_vs_plain(mt, ns),
+                                      workload="16 n log-uniform in [1e13, 1e15], seed 0")
+    return line
+
+
+def workload_batched(args, mt) -> dict:
+    from paper_1108_0135_amd import inputs
+    ns = [int(v) for v in inputs.batch_log_uniform(seed=0, count=256, lo=1e13, hi=1e17)]
+    ns += [10**16, 10**17]
+    res = batched_vs_plain(mt, ns)
+    mt.init(0, 0)
+    out = mt.query(ns)
+    if int(out[-2]) != inputs.TABLE1[10**16] or int(out[-1]) != inputs.TABLE1[10**17]:
+        raise RuntimeError("batched Table 1 values wrong")
+    return {"metric": METRIC, "value": res["batched_qps"], "unit": "queries/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "256 n log-uniform in [1e13,1e17] (seed 0) + 1e16 + 1e17, "
+                                   "one shared sweep vs one at a time"},
+            **res}
+
+
+def workload_serving(args, mt) -> dict:
+    import numpy as np
+    from paper_1108_0135_amd import inputs
+    times, ns = inputs.poisson_trace(seed=0, rate=args.rate, count=args.count)
+    ns = [int(v) for v in ns]
+    # reference values and one-at-a-time service times (FIFO server)
+    mt.init(0, 0)
+    mt.query([10**12])
+    service, ref = [], []
+    for n in ns:
+        t0 = time.perf_counter()
+        ref.append(int(mt.query([n])[0]))
+        service.append(time.perf_counter() - t0)
+    finish, fifo_lat = 0.0, []
+    for a, s in zip(times, service):
+        start = max(a, finish)
+        finish = start + s
+        fifo_lat.append(finish - a)
+    fifo_makespan = finish - times[0]
     mt.shutdown()
+    # serving path: submit at the arrival times, poll until all are done
+    mt.init(0, 0)
+    t_base = time.perf_counter()
+    pending, lat, got = {}, [0.0] * len(ns), [None] * len(ns)
+    i = 0
+    while i < len(ns) or pending:
+        now = time.perf_counter() - t_base
+        while i < len(ns) and times[i] <= now:
+            t = mt.submit(ns[i])
+            if t is None:
+                break
+            pending[t] = i
+            i += 1
+        for t in list(pending):
+            r = mt.poll(t)
+            if r is not None:
+                j = pending.pop(t)
+                got[j], lat[j] = r
+        time.sleep(0.001)
+    makespan = time.perf_counter() - t_base
+    mt.shutdown()
+    if got != ref:
+        raise RuntimeError("served results differ from one-at-a-time results")
+    p = lambda v, q: float(np.percentile(v, q))
+    return {"metric": METRIC, "value": len(ns) / makespan, "unit": "queries/s", "n_gpus": 1,
+            "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": f"Poisson {args.rate} q/s, {args.count} queries, n log-uniform "
+                                   "in [1e10,1e18], seed 0"},
+            "served": {"qps": len(ns) / makespan, "p50_s": p(lat, 50), "p99_s": p(lat, 99)},
+            "fifo_plain": {"qps": len(ns) / fifo_makespan, "p50_s": p(fifo_lat, 50),
+                           "p99_s": p(fifo_lat, 99)}}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", choices=["default", "batched", "serving"], default="default")
+    ap.add_argument("--rate", type=float, default=10.0)
+    ap.add_argument("--count", type=int, default=48)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(DESIGN.md describes how the sweep would shard)", file=sys.stderr)
+        return 2
+
+    from paper_1108_0135_amd import mertens as mt
+    try:
+        if args.workload == "default":
+            line = workload_default(args, mt)
+            if not args.no_cpu_baseline:
+                line["cpu_baseline"] = cpu_baseline()
+        elif args.workload == "batched":
+            line = workload_batched(args, mt)
+        else:
+            line = workload_serving(args, mt)
+    except RuntimeError as e:
+        print(str(e), file=sys.stderr)
+        return 1
+    finally:
+        mt.shutdown()
     print(json.dumps(line), flush=True)
     return 0
 

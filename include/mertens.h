@@ -88,6 +88,37 @@ int mertens_query(const uint64_t *n, size_t count, int64_t *out);
 int mertens_byproducts(size_t i, int64_t *buf, size_t cap, size_t *len);
 
 /*
+ * Serving: asynchronous queries merged into one running sieve sweep.
+ *
+ * mertens_submit -- enqueue M(n) and return a ticket.  A worker thread of
+ * the library runs a cyclic sweep over y-blocks; queued requests join it at
+ * the next block boundary as a batch (admitted while the x entries in
+ * flight, 64 B of device memory each, stay within "serve_x_budget"), so
+ * requests that arrive while others are on the GPU share the sieve with
+ * them (Section 2: one sieve serves several values of n).  Each query uses
+ * u = n^(2/3) (or the u given to mertens_init) and completes as soon as
+ * every block it needs has been visited once since it joined.  Results are
+ * bit-identical to mertens_query.
+ *   n       0 <= n < 2^64 (n = 0 completes at once with M(0) = 0)
+ *   ticket  receives the request id
+ * Returns 0, MERTENS_EAGAIN (already "serve_capacity" requests in flight),
+ * MERTENS_EINVAL (ticket NULL), MERTENS_ENODEV, or the error that stopped
+ * the worker (MERTENS_EIO / MERTENS_ENOMEM).
+ *
+ * mertens_poll -- result of a ticket.  Returns 0 and writes *out = M(n) and
+ * *latency_s = seconds from submit to completion (either pointer may be
+ * NULL; the ticket is then released), MERTENS_EINPROGRESS while pending,
+ * MERTENS_ERANGE for an unknown or already collected ticket, or the error
+ * that stopped the worker.
+ *
+ * The worker uses its own stream and device buffers; mertens_query may be
+ * called meanwhile.  mertens_init and mertens_shutdown stop the worker and
+ * drop uncollected tickets.
+ */
+int mertens_submit(uint64_t n, uint64_t *ticket);
+int mertens_poll(uint64_t ticket, int64_t *out, double *latency_s);
+
+/*
  * mertens_set_stream -- run all further device work on the given HIP stream
  * (a hipStream_t passed as void*; NULL = the library's own stream).  The
  * caller keeps ownership and must keep it alive while the context uses it.
@@ -97,13 +128,17 @@ int mertens_set_stream(void *hip_stream);
 
 /*
  * mertens_set_param -- tuning knobs (results never depend on them).
+ *   "u_scale"     automatic u = u_scale * (sum of the batch's n)^(2/3); default 1
  *   "beta"        split of the per-x sum between the run-length part over
  *                 y <= Y and the explicit k part (K = floor(beta*sqrt(m))),
  *                 in (0, 1]; default 0.2
  *   "ychunk"      y per work item of the run-length part, multiple of 64
  *   "kchunk"      k per work item of the explicit k part
  *   "waves_per_cu" persistent update grid size per compute unit
- * Returns 0 or MERTENS_EINVAL (unknown key or value out of range).
+ *   "serve_capacity"  most requests in flight for mertens_submit (4096)
+ *   "serve_x_budget"  most x entries of admitted requests (2^26 = 4 GiB)
+ * Returns 0 or MERTENS_EINVAL (unknown key, value out of range, or a
+ * non-serving key while the serving worker runs).
  */
 int mertens_set_param(const char *key, double value);
 

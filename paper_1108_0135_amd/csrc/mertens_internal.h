@@ -87,7 +87,9 @@ hipError_t launch_fixup(const BlockArgs &b, hipStream_t s);
 hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
 hipError_t launch_scan_items(const QueryArgs &q, hipStream_t s);
 hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, hipStream_t s);
-hipError_t launch_finalize(const QueryArgs &q, hipStream_t s);
+// qlist = NULL finalizes queries 0..count-1, else the listed query indices
+hipError_t launch_finalize(const QueryArgs &q, const uint32_t *qlist, uint32_t count,
+                           hipStream_t s);
 hipError_t launch_collect(const QueryArgs &q, int64_t *out, hipStream_t s);
 hipError_t launch_debug_div(const uint64_t *n, const uint64_t *d, uint64_t *q, size_t count,
                             hipStream_t s);

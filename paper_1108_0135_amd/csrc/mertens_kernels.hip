@@ -888,50 +888,85 @@ hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, 
 
 // ====================================================================
 // a4: finalize.  A[x] = 1 - S[x] - sum_{k=2}^{floor(L/x)} A[kx], for x from
-// L down to 1 (Section 2), one workgroup per query.  All x with the same
-// j = floor(L/x) form one level whose dependencies lie in earlier levels.
+// L down to 1 (Section 2), one workgroup per query.  The x are taken in
+// dyadic levels (floor(h/2), h]: every dependency kx >= 2x > h lies in an
+// earlier level, so a level's x are independent and there are only
+// ceil(log2 L) + 1 barriers.
 // ====================================================================
 constexpr int FIN_THREADS = 1024;
 
-__global__ __launch_bounds__(FIN_THREADS) void k_finalize(QueryArgs q)
+__global__ __launch_bounds__(FIN_THREADS) void k_finalize(QueryArgs q, const uint32_t *qlist)
 {
-    const uint32_t qi = blockIdx.x;
+    __shared__ uint64_t red[FIN_THREADS / 64];
+    const uint32_t qi = qlist ? qlist[blockIdx.x] : blockIdx.x;
     const uint64_t L = q.q_L[qi];
     const uint64_t g0 = q.q_g0[qi];
     const uint64_t *S = q.S + g0;
     uint64_t *A = reinterpret_cast<uint64_t *>(q.A + g0);  // A[x-1], wrapping arithmetic
     const uint32_t tid = threadIdx.x, lane = lane_id();
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    uint64_t xh = L;
-    while (xh >= 1) {
-        const uint64_t j = L / xh;
-        const uint64_t xl = L / (j + 1);
-        const uint64_t cnt = xh - xl;
-        if (cnt >= 256 || j == 1) {
-            for (uint64_t x = xl + 1 + tid; x <= xh; x += FIN_THREADS) {
+    for (uint64_t hi = L, lo = L / 2; hi >= 1; hi = lo, lo = lo / 2) {
+        const uint64_t nx = hi - lo;  // x in (lo, hi]
+        if (nx >= FIN_THREADS) {
+            for (uint64_t x = lo + 1 + tid; x <= hi; x += FIN_THREADS) {
                 uint64_t s = 1 - S[x - 1];
+                const uint64_t j = L / x;
                 for (uint64_t k = 2; k <= j; ++k)
                     s -= A[k * x - 1];
                 A[x - 1] = s;
             }
-        } else {
-            for (uint64_t x = xl + 1 + wave; x <= xh; x += FIN_THREADS / 64) {
+        } else if (nx > 4) {
+            // groups of gsz lanes (a power of two <= 64) share one x
+            uint32_t gsz = 1;
+            while (gsz < 64 && (uint64_t)gsz * 2 * nx <= FIN_THREADS)
+                gsz *= 2;
+            const uint32_t ngroups = FIN_THREADS / gsz;
+            const uint32_t grp = tid / gsz, sub = tid % gsz;
+            for (uint64_t base = 0; base < nx; base += ngroups) {  // same trip count for all
+                const uint64_t xi = base + grp;
+                const bool active = xi < nx;
+                const uint64_t x = lo + 1 + xi;
                 uint64_t s = 0;
-                for (uint64_t k = 2 + lane; k <= j; k += 64)
+                if (active) {
+                    const uint64_t j = L / x;
+                    for (uint64_t k = 2 + sub; k <= j; k += gsz)
+                        s += A[k * x - 1];
+                }
+                for (uint32_t o = gsz / 2; o >= 1; o >>= 1)
+                    s += __shfl_xor(s, (int)o, 64);
+                if (active && sub == 0)
+                    A[x - 1] = 1 - S[x - 1] - s;
+            }
+        } else {
+            // a handful of x with many terms each: the whole workgroup per x
+            for (uint64_t x = lo + 1; x <= hi; ++x) {
+                const uint64_t j = L / x;
+                uint64_t s = 0;
+                for (uint64_t k = 2 + tid; k <= j; k += FIN_THREADS)
                     s += A[k * x - 1];
                 s = wave_sum_u64(s);
                 if (lane == 0)
-                    A[x - 1] = 1 - S[x - 1] - s;
+                    red[wave] = s;
+                __syncthreads();
+                if (tid == 0) {
+                    uint64_t t = 0;
+                    for (int w = 0; w < FIN_THREADS / 64; ++w)
+                        t += red[w];
+                    A[x - 1] = 1 - S[x - 1] - t;
+                }
+                __syncthreads();
             }
         }
         __syncthreads();
-        xh = xl;
     }
 }
 
-hipError_t launch_finalize(const QueryArgs &q, hipStream_t s)
+hipError_t launch_finalize(const QueryArgs &q, const uint32_t *qlist, uint32_t count,
+                           hipStream_t s)
 {
-    hipLaunchKernelGGL(k_finalize, dim3(q.nq), dim3(FIN_THREADS), 0, s, q);
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3(count), dim3(FIN_THREADS), 0, s, q, qlist);
     return hipGetLastError();
 }
 

@@ -1,36 +1,55 @@
 // Host runtime and C ABI of the gfx950 Mertens library (see include/mertens.h).
 //
-// The runtime plans a sweep (Section 2 blocking: u, L per query, sieve limit,
-// sieving primes), owns every device buffer, and issues the per-block kernel
-// sequence of Section 3 on one HIP stream:
-//   block setup -> sieve -> segment scan -> fixup -> update prep -> item scan
-//   -> persistent update
-// followed by finalize and collect.  No host synchronisation happens inside
-// the sweep; the host only waits for the final results.
+// Two engines share the same building blocks:
+//   * the synchronous path (mertens_query): one Batch of queries, one sweep
+//     over y-blocks 0, 1, ... in order, then finalize;
+//   * the serving path (mertens_submit / mertens_poll): a worker thread runs
+//     a cyclic sweep; requests join at the next block boundary as a new
+//     Batch, each query completes once every block it needs has been
+//     visited once since it joined (contributions commute, so the order of
+//     blocks does not matter; within a pass the sieve carry runs in
+//     ascending y), and is finalized and returned on its own.
+// Per block the kernel sequence is (Section 3):
+//   residues -> sieve -> square fix -> word prefix -> segment prefix ->
+//   fixup -> update prep -> item prefix -> persistent update
+// with no host synchronisation inside a sweep.
 #include "mertens.h"
 #include "mertens_internal.h"
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdio>
 #include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 using namespace mrt;
 
 namespace {
 
+std::mutex g_err_mu;
 std::string g_last_error = "no error";
 
 void set_error(const char *what, hipError_t e, const char *file, int line)
 {
     char buf[512];
     snprintf(buf, sizeof buf, "%s failed: %s (%s:%d)", what, hipGetErrorString(e), file, line);
+    std::lock_guard<std::mutex> lk(g_err_mu);
     g_last_error = buf;
 }
 
-void set_error_text(const char *text) { g_last_error = text; }
+void set_error_text(const char *text)
+{
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    g_last_error = text;
+}
 
 #define HIPCHK(expr)                                         \
     do {                                                     \
@@ -47,6 +66,12 @@ void set_error_text(const char *text) { g_last_error = text; }
         if (rc_ != 0)            \
             return rc_;          \
     } while (0)
+
+double now_s()
+{
+    using namespace std::chrono;
+    return duration<double>(steady_clock::now().time_since_epoch()).count();
+}
 
 struct DevBuf {
     void *p = nullptr;
@@ -104,6 +129,365 @@ uint8_t log_prime_host(uint64_t p)
     return (uint8_t)(l | 1u);  // ceil(log2 p) | 1
 }
 
+// scale * N^(2/3): with a sieve cost proportional to u and an update cost
+// proportional to (sum of n)/sqrt(u), the total is smallest at u ~ (sum n)^(2/3)
+// (Section 2, and its remark on several close values of n); the scale is
+// the tuned ratio of the two costs.
+uint64_t auto_u(long double total_n, double scale)
+{
+    const double v = scale * std::pow((double)total_n, 2.0 / 3.0);
+    uint64_t u = (uint64_t)std::ceil(v > 1.8e19 ? 1.8e19 : v);
+    return u < 2 ? 2 : u;
+}
+
+struct Tuning {
+    double u_scale = 1.0;  // automatic u = u_scale * (sum of the batch's n)^(2/3)
+    double beta = 0.2;
+    uint32_t ychunk = 4096, kchunk = 2048, klchunk = 256, waves_per_cu = 16;
+};
+
+// ---------------------------------------------------------------------------
+// Device tables and block buffers of one sweep engine.
+// ---------------------------------------------------------------------------
+struct SieveState {
+    uint64_t psieve = 0;
+    std::vector<uint32_t> h_primes;  // primes >= 5 up to psieve
+    DevBuf pres, res2, pattern, masks, mb, seg_sum, seg_off, carry;
+    bool have_pattern = false;
+
+    void release()
+    {
+        DevBuf *bufs[] = {&pres, &res2, &pattern, &masks, &mb, &seg_sum, &seg_off, &carry};
+        for (DevBuf *b : bufs)
+            b->release();
+        h_primes.clear();
+        psieve = 0;
+        have_pattern = false;
+    }
+
+    // Sieving primes p in [5, limit] (plain Eratosthenes on odd numbers) and
+    // their device copy as {p, residue} pairs.  Grows only.
+    int ensure_primes(uint64_t limit)
+    {
+        if (limit <= psieve)
+            return 0;
+        std::vector<uint8_t> comp(limit / 2 + 1, 0);  // comp[i] <=> 2i+1 composite
+        for (uint64_t i = 3; i * i <= limit; i += 2)
+            if (!comp[i / 2])
+                for (uint64_t j = i * i; j <= limit; j += 2 * i)
+                    comp[j / 2] = 1;
+        std::vector<uint32_t> pr, pairs;
+        for (uint64_t v = 5; v <= limit; v += 2)
+            if (!comp[v / 2]) {
+                pr.push_back((uint32_t)v);
+                pairs.push_back((uint32_t)v);
+                pairs.push_back(0u);
+            }
+        const size_t np = pr.size();
+        RCCHK(ensure(pres, np * 8));
+        RCCHK(ensure(res2, np * 8));
+        HIPCHK(hipMemcpy(pres.p, pairs.data(), np * 8, hipMemcpyHostToDevice));
+        h_primes.swap(pr);
+        psieve = limit;
+        return 0;
+    }
+
+    // Pattern of the modified sieve for the primes 2, 3, 5, 7, 11, 13 and the
+    // squares 4, 9 (period 180180), extended by one segment so a segment's
+    // initial state is one straight copy.
+    int ensure_pattern()
+    {
+        if (have_pattern)
+            return 0;
+        const uint32_t small[6] = {2, 3, 5, 7, 11, 13};
+        std::vector<uint8_t> pat((size_t)PAT_WORDS * 4, 0);
+        for (size_t i = 0; i < pat.size(); ++i) {
+            const uint32_t r = (uint32_t)(i % PAT);
+            uint32_t a = 0;
+            for (uint32_t p : small)
+                if (r % p == 0)
+                    a += log_prime_host(p);
+            if (r % 4 == 0 || r % 9 == 0)
+                a |= 0x80u;
+            pat[i] = (uint8_t)a;
+        }
+        RCCHK(ensure(pattern, pat.size()));
+        HIPCHK(hipMemcpy(pattern.p, pat.data(), pat.size(), hipMemcpyHostToDevice));
+        have_pattern = true;
+        return 0;
+    }
+
+    int ensure_blocks(uint64_t B)
+    {
+        RCCHK(ensure(masks, B / 64 * 16));
+        RCCHK(ensure(mb, B / 64 * 8));
+        RCCHK(ensure(seg_sum, B / SEG * 4));
+        RCCHK(ensure(seg_off, B / SEG * 8));
+        RCCHK(ensure(carry, 64));
+        return 0;
+    }
+
+    uint32_t count_primes_upto(uint64_t v) const  // # table primes p <= v
+    {
+        return (uint32_t)(std::upper_bound(h_primes.begin(), h_primes.end(), v,
+                                           [](uint64_t a, uint32_t b) { return a < b; }) -
+                          h_primes.begin());
+    }
+
+    BlockArgs make_block(uint64_t y1, uint64_t y2) const
+    {
+        BlockArgs b;
+        b.y1 = y1;
+        b.y2 = y2;
+        b.nseg = (uint32_t)((y2 - y1) / SEG + 1);
+        b.n_small = count_primes_upto(SMALL_P - 1);
+        b.n_sieve = (uint32_t)h_primes.size();
+        b.n_sq = count_primes_upto(isqrt_host(y2));
+        b.n_sq_lds = std::min(count_primes_upto(SQ_LDS_P), b.n_sq);
+        b.pat_off = (uint32_t)(y1 % PAT);
+        b.pres = pres.as<uint2>();
+        b.res2 = res2.as<uint64_t>();
+        b.pat32 = pattern.as<uint32_t>();
+        b.masks = masks.as<uint64_t>();
+        b.mb = mb.as<int64_t>();
+        b.seg_sum = seg_sum.as<int32_t>();
+        b.seg_off = seg_off.as<int64_t>();
+        b.carry = carry.as<int64_t>();
+        return b;
+    }
+
+    // residues, then the sieve (an event may be recorded in between so the
+    // sieve kernels are timed alone), then the large-square fix
+    int sieve(const BlockArgs &b, hipStream_t s, hipEvent_t between) const
+    {
+        HIPCHK(launch_block_setup(b, s));
+        if (between)
+            HIPCHK(hipEventRecord(between, s));
+        HIPCHK(launch_sieve(b, s));
+        HIPCHK(launch_square_fix(b, s));
+        return 0;
+    }
+
+    int scan(const BlockArgs &b, hipStream_t s) const
+    {
+        HIPCHK(launch_scan_words(b, s));
+        HIPCHK(launch_scan_segments(b, s));
+        HIPCHK(launch_fixup(b, s));
+        return 0;
+    }
+
+    int reset_carry(hipStream_t s) const
+    {
+        HIPCHK(launch_zero_u64(reinterpret_cast<uint64_t *>(carry.p), 1, s));
+        return 0;
+    }
+};
+
+// ---------------------------------------------------------------------------
+// One set of queries sharing a sweep: per-query plan and device state.
+// ---------------------------------------------------------------------------
+struct Batch {
+    std::vector<uint64_t> n, L, g0, ymax;
+    uint64_t X = 0, ymax_all = 0;
+    uint32_t ntiles = 0;
+    DevBuf q_n, q_L, q_g0, x_m, x_Y, x_K, x_k0, S, A, x_klo, x_khi;
+    DevBuf tile_q, tile_x0, tile_nx, tile_g0, tile_ymax, tile_klo, tile_khi, tile_mode, tile_nmu,
+        tile_items, counter, pair_stats, out_dev, qlist;
+    QueryArgs args{};
+
+    void release()
+    {
+        DevBuf *bufs[] = {&q_n, &q_L, &q_g0, &x_m, &x_Y, &x_K, &x_k0, &S, &A, &x_klo, &x_khi,
+                          &tile_q, &tile_x0, &tile_nx, &tile_g0, &tile_ymax, &tile_klo,
+                          &tile_khi, &tile_mode, &tile_nmu, &tile_items, &counter, &pair_stats,
+                          &out_dev, &qlist};
+        for (DevBuf *b : bufs)
+            b->release();
+    }
+
+    // Plan the queries ns[i] with split us[i] (Section 2: L = max(1, n/u)
+    // array entries; the sieve covers [1, n/(L+1)]).
+    int plan(const std::vector<uint64_t> &ns, const std::vector<uint64_t> &us, const Tuning &t,
+             hipStream_t s)
+    {
+        const size_t nq = ns.size();
+        n = ns;
+        L.assign(nq, 0);
+        g0.assign(nq, 0);
+        ymax.assign(nq, 0);
+        X = 0;
+        ymax_all = 0;
+        for (size_t i = 0; i < nq; ++i) {
+            uint64_t Li = ns[i] / us[i];
+            if (Li < 1)
+                Li = 1;
+            if (Li >= (1ull << 31)) {
+                set_error_text("u too small: some n would need an array of 2^31 or more entries");
+                return MERTENS_EINVAL;
+            }
+            L[i] = Li;
+            g0[i] = X;
+            X += Li;
+            ymax[i] = ns[i] / (Li + 1);
+            ymax_all = std::max(ymax_all, ymax[i]);
+        }
+        std::vector<uint32_t> t_q, t_x0, t_nx;
+        std::vector<uint64_t> t_g0;
+        for (size_t i = 0; i < nq; ++i)
+            for (uint64_t x0 = 1; x0 <= L[i]; x0 += TILE) {
+                t_q.push_back((uint32_t)i);
+                t_x0.push_back((uint32_t)x0);
+                t_nx.push_back((uint32_t)std::min<uint64_t>(TILE, L[i] - x0 + 1));
+                t_g0.push_back(g0[i] + x0 - 1);
+            }
+        const size_t nt = t_q.size();
+        if (nt >= (1ull << 31)) {
+            set_error_text("too many tiles");
+            return MERTENS_EINVAL;
+        }
+        ntiles = (uint32_t)nt;
+        RCCHK(ensure(q_n, nq * 8));
+        RCCHK(ensure(q_L, nq * 8));
+        RCCHK(ensure(q_g0, nq * 8));
+        DevBuf *xb[] = {&x_m, &x_Y, &x_K, &x_k0, &S, &A, &x_klo, &x_khi};
+        for (DevBuf *b : xb)
+            RCCHK(ensure(*b, X * 8));
+        RCCHK(ensure(tile_q, nt * 4));
+        RCCHK(ensure(tile_x0, nt * 4));
+        RCCHK(ensure(tile_nx, nt * 4));
+        RCCHK(ensure(tile_mode, nt * 4));
+        RCCHK(ensure(tile_nmu, nt * 4));
+        RCCHK(ensure(tile_g0, nt * 8));
+        RCCHK(ensure(tile_ymax, nt * 8));
+        RCCHK(ensure(tile_klo, nt * 8));
+        RCCHK(ensure(tile_khi, nt * 8));
+        RCCHK(ensure(tile_items, (nt + 1) * 8));
+        RCCHK(ensure(counter, 64));
+        RCCHK(ensure(pair_stats, 64));
+        RCCHK(ensure(out_dev, nq * 8));
+        RCCHK(ensure(qlist, nq * 4));
+        HIPCHK(hipMemcpyAsync(q_n.p, n.data(), nq * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(q_L.p, L.data(), nq * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(q_g0.p, g0.data(), nq * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(tile_q.p, t_q.data(), nt * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(tile_x0.p, t_x0.data(), nt * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(tile_nx.p, t_nx.data(), nt * 4, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(tile_g0.p, t_g0.data(), nt * 8, hipMemcpyHostToDevice, s));
+        // pageable sources: make sure the copies are done before they go away
+        HIPCHK(hipStreamSynchronize(s));
+
+        QueryArgs &q = args;
+        q.nq = (uint32_t)nq;
+        q.q_n = q_n.as<uint64_t>();
+        q.q_L = q_L.as<uint64_t>();
+        q.q_g0 = q_g0.as<uint64_t>();
+        q.x_m = x_m.as<uint64_t>();
+        q.x_Y = x_Y.as<uint64_t>();
+        q.x_K = x_K.as<uint64_t>();
+        q.x_k0 = x_k0.as<uint64_t>();
+        q.S = S.as<uint64_t>();
+        q.A = A.as<int64_t>();
+        q.x_klo = x_klo.as<uint64_t>();
+        q.x_khi = x_khi.as<uint64_t>();
+        q.ntiles = ntiles;
+        q.tile_q = tile_q.as<uint32_t>();
+        q.tile_x0 = tile_x0.as<uint32_t>();
+        q.tile_nx = tile_nx.as<uint32_t>();
+        q.tile_g0 = tile_g0.as<uint64_t>();
+        q.tile_ymax = tile_ymax.as<uint64_t>();
+        q.tile_klo = tile_klo.as<uint64_t>();
+        q.tile_khi = tile_khi.as<uint64_t>();
+        q.tile_mode = tile_mode.as<uint32_t>();
+        q.tile_nmu = tile_nmu.as<uint32_t>();
+        q.tile_items = tile_items.as<uint64_t>();
+        q.counter = counter.as<uint32_t>();
+        q.pair_stats = pair_stats.as<uint64_t>();
+        q.beta = t.beta;
+        q.ychunk = t.ychunk;
+        q.kchunk = t.kchunk;
+        q.klchunk = t.klchunk;
+        HIPCHK(launch_zero_u64(pair_stats.as<uint64_t>(), 4, s));
+        HIPCHK(launch_plan(q, s));
+        return 0;
+    }
+
+    // update prep and item prefix, [event], persistent update
+    int update_block(const BlockArgs &b, uint32_t grid, hipStream_t s, hipEvent_t mid) const
+    {
+        HIPCHK(launch_update_prep(args, b, s));
+        HIPCHK(launch_scan_items(args, s));
+        if (mid)
+            HIPCHK(hipEventRecord(mid, s));
+        HIPCHK(launch_update(args, b, grid, s));
+        return 0;
+    }
+
+    // Finalize the listed queries (all when `which` is empty) and gather
+    // every A[1] into out_dev.
+    int finalize(const std::vector<uint32_t> &which, hipStream_t s)
+    {
+        if (which.empty()) {
+            HIPCHK(launch_finalize(args, nullptr, args.nq, s));
+        } else {
+            HIPCHK(hipMemcpyAsync(qlist.p, which.data(), which.size() * 4, hipMemcpyHostToDevice,
+                                  s));
+            HIPCHK(launch_finalize(args, qlist.as<uint32_t>(), (uint32_t)which.size(), s));
+        }
+        HIPCHK(launch_collect(args, out_dev.as<int64_t>(), s));
+        return 0;
+    }
+};
+
+uint32_t update_grid(int ncu, const Tuning &t)
+{
+    return (uint32_t)std::max(1, ncu * (int)t.waves_per_cu / (UPD_THREADS / 64));
+}
+
+uint64_t choose_block(uint64_t req, uint64_t ymax)
+{
+    if (req)
+        return req;
+    const uint64_t need = (ymax / SEG + 1) * SEG;
+    return std::min<uint64_t>(need, 1ull << 30);
+}
+
+// ---------------------------------------------------------------------------
+// Serving engine
+// ---------------------------------------------------------------------------
+struct ServeQuery {
+    uint64_t n = 0;
+    double t_submit = 0, latency = 0;
+    int64_t result = 0;
+    int state = 0;  // 0 queued, 1 in the sweep, 2 done, 3 failed
+    uint32_t idx = 0;
+    uint64_t last_block = 0, seen = 0;
+    std::vector<uint8_t> seen_map;
+};
+
+struct ServeBatch {
+    Batch b;
+    std::vector<uint64_t> tickets;
+    size_t open = 0;  // queries not yet finalized
+    uint64_t x_entries = 0;
+};
+
+struct Server {
+    std::thread worker;
+    std::mutex mu;
+    std::condition_variable cv;
+    bool running = false, stop = false;
+    int failure = 0;
+    hipStream_t stream = nullptr;
+    SieveState ss;
+    std::deque<uint64_t> queued;
+    std::map<uint64_t, ServeQuery> queries;
+    std::vector<std::unique_ptr<ServeBatch>> batches;  // worker thread only
+    uint64_t next_ticket = 1;
+    uint64_t x_used = 0;
+    uint64_t cur_block = 0;
+    uint64_t blocks_run = 0;
+};
+
 struct Ctx {
     bool ready = false;
     int device = 0;
@@ -111,38 +495,28 @@ struct Ctx {
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
     uint64_t u_req = 0, block_req = 0;
-    // tuning
-    double beta = 0.2;
-    uint32_t ychunk = 4096, kchunk = 2048, klchunk = 256, waves_per_cu = 16;
-    // sieving primes (>= 5) up to psieve, and the pre-sieved pattern
-    uint64_t psieve = 0;
-    std::vector<uint32_t> h_primes;
-    DevBuf pres, res2, pattern;
-    // block buffers
-    DevBuf masks, mb, seg_sum, seg_off, carry;
-    // query buffers
-    DevBuf q_n, q_L, q_g0, x_m, x_Y, x_K, x_k0, S, A, x_klo, x_khi;
-    DevBuf tile_q, tile_x0, tile_nx, tile_g0, tile_ymax, tile_klo, tile_khi, tile_mode, tile_nmu,
-        tile_items, counter, pair_stats, out_dev;
+    Tuning tune;
+    size_t serve_capacity = 4096;
+    uint64_t serve_x_budget = 1ull << 26;  // x entries in flight (64 B each)
+    SieveState ss;
+    Batch batch;
     // last query (for byproducts): per caller index, L and first global index
     std::vector<uint64_t> last_L, last_g0;
     bool last_valid = false;
     double stats[16] = {0};
     std::vector<hipEvent_t> events;
+    Server srv;
 };
 
 Ctx g;
 
+void serve_stop();
+
 void free_all()
 {
-    DevBuf *bufs[] = {&g.pres, &g.res2, &g.pattern, &g.masks, &g.mb,
-                      &g.seg_sum, &g.seg_off, &g.carry, &g.q_n, &g.q_L, &g.q_g0, &g.x_m,
-                      &g.x_Y, &g.x_K, &g.x_k0, &g.S, &g.A, &g.x_klo, &g.x_khi, &g.tile_q,
-                      &g.tile_x0, &g.tile_nx, &g.tile_g0, &g.tile_ymax, &g.tile_klo,
-                      &g.tile_khi, &g.tile_mode, &g.tile_nmu, &g.tile_items, &g.counter,
-                      &g.pair_stats, &g.out_dev};
-    for (DevBuf *b : bufs)
-        b->release();
+    serve_stop();
+    g.ss.release();
+    g.batch.release();
     for (hipEvent_t e : g.events)
         (void)hipEventDestroy(e);
     g.events.clear();
@@ -150,128 +524,10 @@ void free_all()
         (void)hipStreamDestroy(g.own_stream);
     g.own_stream = nullptr;
     g.stream = nullptr;
-    g.h_primes.clear();
-    g.psieve = 0;
     g.last_L.clear();
     g.last_g0.clear();
     g.last_valid = false;
     g.ready = false;
-}
-
-// Sieving primes p in [5, limit] (plain Eratosthenes on odd numbers) and
-// their device copy as {p, residue} pairs.  Grows only.
-int ensure_primes(uint64_t limit)
-{
-    if (limit <= g.psieve)
-        return 0;
-    std::vector<uint8_t> comp(limit / 2 + 1, 0);  // comp[i] <=> 2i+1 composite
-    for (uint64_t i = 3; i * i <= limit; i += 2)
-        if (!comp[i / 2])
-            for (uint64_t j = i * i; j <= limit; j += 2 * i)
-                comp[j / 2] = 1;
-    std::vector<uint32_t> pr, pairs;
-    for (uint64_t v = 5; v <= limit; v += 2)
-        if (!comp[v / 2]) {
-            pr.push_back((uint32_t)v);
-            pairs.push_back((uint32_t)v);
-            pairs.push_back(0u);
-        }
-    const size_t np = pr.size();
-    RCCHK(ensure(g.pres, np * 8));
-    RCCHK(ensure(g.res2, np * 8));
-    HIPCHK(hipMemcpy(g.pres.p, pairs.data(), np * 8, hipMemcpyHostToDevice));
-    g.h_primes.swap(pr);
-    g.psieve = limit;
-    return 0;
-}
-
-// Pattern of the modified sieve for the primes 2, 3, 5, 7, 11, 13 and the
-// squares 4, 9 (period 180180), extended by one segment so a segment's
-// initial state is one straight copy.
-int upload_pattern()
-{
-    const uint32_t small[6] = {2, 3, 5, 7, 11, 13};
-    std::vector<uint8_t> pat((size_t)PAT_WORDS * 4, 0);
-    for (size_t i = 0; i < pat.size(); ++i) {
-        const uint32_t r = (uint32_t)(i % PAT);
-        uint32_t a = 0;
-        for (uint32_t p : small)
-            if (r % p == 0)
-                a += log_prime_host(p);
-        if (r % 4 == 0 || r % 9 == 0)
-            a |= 0x80u;
-        pat[i] = (uint8_t)a;
-    }
-    RCCHK(ensure(g.pattern, pat.size()));
-    HIPCHK(hipMemcpy(g.pattern.p, pat.data(), pat.size(), hipMemcpyHostToDevice));
-    return 0;
-}
-
-uint32_t count_primes_upto(uint64_t v)  // # table primes p <= v
-{
-    return (uint32_t)(std::upper_bound(g.h_primes.begin(), g.h_primes.end(),
-                                       (uint64_t)v,
-                                       [](uint64_t a, uint32_t b) { return a < b; }) -
-                      g.h_primes.begin());
-}
-
-uint32_t count_squares_upto(uint64_t v)  // # table primes with p^2 <= v
-{
-    return count_primes_upto(isqrt_host(v));
-}
-
-int ensure_block_buffers(uint64_t B)
-{
-    const uint64_t words = B / 64;
-    const uint64_t nseg = B / SEG;
-    RCCHK(ensure(g.masks, words * 16));
-    RCCHK(ensure(g.mb, words * 8));
-    RCCHK(ensure(g.seg_sum, nseg * 4));
-    RCCHK(ensure(g.seg_off, nseg * 8));
-    RCCHK(ensure(g.carry, 64));
-    return 0;
-}
-
-BlockArgs make_block(uint64_t y1, uint64_t y2)
-{
-    BlockArgs b;
-    b.y1 = y1;
-    b.y2 = y2;
-    b.nseg = (uint32_t)((y2 - y1) / SEG + 1);
-    b.n_small = count_primes_upto(SMALL_P - 1);
-    b.n_sieve = (uint32_t)g.h_primes.size();
-    b.n_sq = count_squares_upto(y2);
-    b.n_sq_lds = std::min(count_primes_upto(SQ_LDS_P), b.n_sq);
-    b.pat_off = (uint32_t)(y1 % PAT);
-    b.pres = g.pres.as<uint2>();
-    b.res2 = g.res2.as<uint64_t>();
-    b.pat32 = g.pattern.as<uint32_t>();
-    b.masks = g.masks.as<uint64_t>();
-    b.mb = g.mb.as<int64_t>();
-    b.seg_sum = g.seg_sum.as<int32_t>();
-    b.seg_off = g.seg_off.as<int64_t>();
-    b.carry = g.carry.as<int64_t>();
-    return b;
-}
-
-// Sieve one block: residue setup, then the sieve kernel (an event may be
-// recorded between the two so the sieve kernel is timed alone).
-int sieve_block(const BlockArgs &b, hipEvent_t between = nullptr)
-{
-    HIPCHK(launch_block_setup(b, g.stream));
-    if (between)
-        HIPCHK(hipEventRecord(between, g.stream));
-    HIPCHK(launch_sieve(b, g.stream));
-    HIPCHK(launch_square_fix(b, g.stream));
-    return 0;
-}
-
-int scan_block(const BlockArgs &b)
-{
-    HIPCHK(launch_scan_words(b, g.stream));
-    HIPCHK(launch_scan_segments(b, g.stream));
-    HIPCHK(launch_fixup(b, g.stream));
-    return 0;
 }
 
 hipEvent_t event_at(size_t i)
@@ -293,176 +549,58 @@ float elapsed(size_t a, size_t b)
     return ms;
 }
 
-uint64_t choose_block(uint64_t ymax)
-{
-    if (g.block_req)
-        return g.block_req;
-    uint64_t need = (ymax / SEG + 1) * SEG;
-    return std::min<uint64_t>(need, 1ull << 30);
-}
-
-// The sweep for nonzero arguments ns[]: fills A on the device and the
-// results into res[] (host).
-int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
-              std::vector<uint64_t> &Ls, std::vector<uint64_t> &g0s)
+// The synchronous sweep for nonzero arguments ns[]: fills A on the device
+// and the results into res[] (host).
+int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
 {
     const size_t nq = ns.size();
-    // ---- plan (a0): u, L, sieve limit
     uint64_t u = g.u_req;
     if (u == 0) {
         long double sum = 0;
-        for (uint64_t n : ns)
-            sum += (long double)n;
-        u = (uint64_t)std::ceil(std::pow((double)sum, 2.0 / 3.0));
-        if (u < 2)
-            u = 2;
+        for (uint64_t v : ns)
+            sum += (long double)v;
+        u = auto_u(sum, g.tune.u_scale);
     }
-    Ls.resize(nq);
-    g0s.resize(nq);
-    uint64_t X = 0, ymax = 0;
-    for (size_t i = 0; i < nq; ++i) {
-        uint64_t L = ns[i] / u;
-        if (L < 1)
-            L = 1;
-        if (L >= (1ull << 31)) {
-            set_error_text("u too small: some n would need an array of 2^31 or more entries");
-            return MERTENS_EINVAL;
-        }
-        Ls[i] = L;
-        g0s[i] = X;
-        X += L;
-        ymax = std::max<uint64_t>(ymax, ns[i] / (L + 1));
-    }
-    // tiles of 64 consecutive x per query
-    std::vector<uint32_t> t_q, t_x0, t_nx;
-    std::vector<uint64_t> t_g0;
-    for (size_t i = 0; i < nq; ++i)
-        for (uint64_t x0 = 1; x0 <= Ls[i]; x0 += TILE) {
-            t_q.push_back((uint32_t)i);
-            t_x0.push_back((uint32_t)x0);
-            t_nx.push_back((uint32_t)std::min<uint64_t>(TILE, Ls[i] - x0 + 1));
-            t_g0.push_back(g0s[i] + x0 - 1);
-        }
-    const size_t nt = t_q.size();
-    if (nt >= (1ull << 31)) {
-        set_error_text("too many tiles");
-        return MERTENS_EINVAL;
-    }
-
-    const uint64_t psieve = std::max<uint64_t>(ceil_sqrt_host(ymax), 1024);
-    RCCHK(ensure_primes(psieve));
-    const uint64_t B = choose_block(ymax);
-    RCCHK(ensure_block_buffers(B));
-
-    RCCHK(ensure(g.q_n, nq * 8));
-    RCCHK(ensure(g.q_L, nq * 8));
-    RCCHK(ensure(g.q_g0, nq * 8));
-    DevBuf *xb[] = {&g.x_m, &g.x_Y, &g.x_K, &g.x_k0, &g.S, &g.A, &g.x_klo, &g.x_khi};
-    for (DevBuf *b : xb)
-        RCCHK(ensure(*b, X * 8));
-    RCCHK(ensure(g.tile_q, nt * 4));
-    RCCHK(ensure(g.tile_x0, nt * 4));
-    RCCHK(ensure(g.tile_nx, nt * 4));
-    RCCHK(ensure(g.tile_mode, nt * 4));
-    RCCHK(ensure(g.tile_nmu, nt * 4));
-    RCCHK(ensure(g.tile_g0, nt * 8));
-    RCCHK(ensure(g.tile_ymax, nt * 8));
-    RCCHK(ensure(g.tile_klo, nt * 8));
-    RCCHK(ensure(g.tile_khi, nt * 8));
-    RCCHK(ensure(g.tile_items, (nt + 1) * 8));
-    RCCHK(ensure(g.counter, 64));
-    RCCHK(ensure(g.pair_stats, 64));
-    RCCHK(ensure(g.out_dev, nq * 8));
-
     hipStream_t s = g.stream;
-    HIPCHK(hipMemcpyAsync(g.q_n.p, ns.data(), nq * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(g.q_L.p, Ls.data(), nq * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(g.q_g0.p, g0s.data(), nq * 8, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(g.tile_q.p, t_q.data(), nt * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(g.tile_x0.p, t_x0.data(), nt * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(g.tile_nx.p, t_nx.data(), nt * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(hipMemcpyAsync(g.tile_g0.p, t_g0.data(), nt * 8, hipMemcpyHostToDevice, s));
-
-    QueryArgs q;
-    q.nq = (uint32_t)nq;
-    q.q_n = g.q_n.as<uint64_t>();
-    q.q_L = g.q_L.as<uint64_t>();
-    q.q_g0 = g.q_g0.as<uint64_t>();
-    q.x_m = g.x_m.as<uint64_t>();
-    q.x_Y = g.x_Y.as<uint64_t>();
-    q.x_K = g.x_K.as<uint64_t>();
-    q.x_k0 = g.x_k0.as<uint64_t>();
-    q.S = g.S.as<uint64_t>();
-    q.A = g.A.as<int64_t>();
-    q.x_klo = g.x_klo.as<uint64_t>();
-    q.x_khi = g.x_khi.as<uint64_t>();
-    q.ntiles = (uint32_t)nt;
-    q.tile_q = g.tile_q.as<uint32_t>();
-    q.tile_x0 = g.tile_x0.as<uint32_t>();
-    q.tile_nx = g.tile_nx.as<uint32_t>();
-    q.tile_g0 = g.tile_g0.as<uint64_t>();
-    q.tile_ymax = g.tile_ymax.as<uint64_t>();
-    q.tile_klo = g.tile_klo.as<uint64_t>();
-    q.tile_khi = g.tile_khi.as<uint64_t>();
-    q.tile_mode = g.tile_mode.as<uint32_t>();
-    q.tile_nmu = g.tile_nmu.as<uint32_t>();
-    q.tile_items = g.tile_items.as<uint64_t>();
-    q.counter = g.counter.as<uint32_t>();
-    q.pair_stats = g.pair_stats.as<uint64_t>();
-    q.beta = g.beta;
-    q.ychunk = g.ychunk;
-    q.kchunk = g.kchunk;
-    q.klchunk = g.klchunk;
-
+    Batch &bt = g.batch;
+    RCCHK(bt.plan(ns, std::vector<uint64_t>(nq, u), g.tune, s));
+    const uint64_t ymax = bt.ymax_all;
+    RCCHK(g.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(ymax), 1024)));
+    RCCHK(g.ss.ensure_pattern());
+    const uint64_t B = choose_block(g.block_req, ymax);
+    RCCHK(g.ss.ensure_blocks(B));
     const uint64_t nblocks = ymax / B + 1;
+    const uint32_t grid = update_grid(g.ncu, g.tune);
+
     size_t ev = 0;
-    hipEvent_t e_start = event_at(ev++);
-    if (!e_start) {
+    if (!event_at(5 * nblocks + 3)) {
         set_error_text("hipEventCreate failed");
         return MERTENS_EIO;
     }
-    HIPCHK(hipEventRecord(e_start, s));
-    HIPCHK(launch_zero_u64(g.pair_stats.as<uint64_t>(), 4, s));
-    HIPCHK(launch_zero_u64(reinterpret_cast<uint64_t *>(g.carry.p), 1, s));
-    HIPCHK(launch_plan(q, s));
-    const uint32_t grid = (uint32_t)std::max(1, g.ncu * (int)g.waves_per_cu / (UPD_THREADS / 64));
+    HIPCHK(hipEventRecord(g.events[ev++], s));
+    RCCHK(g.ss.reset_carry(s));
     std::vector<size_t> marks;
-    marks.reserve(nblocks * 5);
+    marks.reserve(nblocks);
     for (uint64_t bi = 0; bi < nblocks; ++bi) {
         const uint64_t y1 = bi * B;
         const uint64_t y2 = std::min(y1 + B - 1, ymax);
-        const BlockArgs b = make_block(y1, y2);
-        hipEvent_t e0 = event_at(ev), e1 = event_at(ev + 1), e2 = event_at(ev + 2),
-                   e3 = event_at(ev + 3), e4 = event_at(ev + 4);
-        if (!e0 || !e1 || !e2 || !e3 || !e4) {
-            set_error_text("hipEventCreate failed");
-            return MERTENS_EIO;
-        }
+        const BlockArgs b = g.ss.make_block(y1, y2);
         marks.push_back(ev);
+        RCCHK(g.ss.sieve(b, s, g.events[ev]));
+        HIPCHK(hipEventRecord(g.events[ev + 1], s));
+        RCCHK(g.ss.scan(b, s));
+        HIPCHK(hipEventRecord(g.events[ev + 2], s));
+        RCCHK(bt.update_block(b, grid, s, g.events[ev + 3]));
+        HIPCHK(hipEventRecord(g.events[ev + 4], s));
         ev += 5;
-        RCCHK(sieve_block(b, e0));
-        HIPCHK(hipEventRecord(e1, s));
-        RCCHK(scan_block(b));
-        HIPCHK(hipEventRecord(e2, s));
-        HIPCHK(launch_update_prep(q, b, s));
-        HIPCHK(launch_scan_items(q, s));
-        HIPCHK(hipEventRecord(e3, s));
-        HIPCHK(launch_update(q, b, grid, s));
-        HIPCHK(hipEventRecord(e4, s));
     }
-    hipEvent_t ef0 = event_at(ev), ef1 = event_at(ev + 1);
-    if (!ef0 || !ef1) {
-        set_error_text("hipEventCreate failed");
-        return MERTENS_EIO;
-    }
-    HIPCHK(hipEventRecord(ef0, s));
-    HIPCHK(launch_finalize(q, s));
-    HIPCHK(hipEventRecord(ef1, s));
-    HIPCHK(launch_collect(q, g.out_dev.as<int64_t>(), s));
+    HIPCHK(hipEventRecord(g.events[ev], s));
+    RCCHK(bt.finalize({}, s));
+    HIPCHK(hipEventRecord(g.events[ev + 1], s));
     res.resize(nq);
     uint64_t pst[4] = {0, 0, 0, 0};
-    HIPCHK(hipMemcpyAsync(res.data(), g.out_dev.p, nq * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(pst, g.pair_stats.p, 32, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(res.data(), bt.out_dev.p, nq * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pst, bt.pair_stats.p, 32, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
 
     double t_sieve = 0, t_scan = 0, t_prep = 0, t_upd = 0;
@@ -475,7 +613,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     g.stats[0] = (double)(ymax + 1);
     g.stats[1] = (double)nblocks;
     g.stats[2] = (double)u;
-    g.stats[3] = (double)X;
+    g.stats[3] = (double)bt.X;
     g.stats[4] = (double)pst[0];
     g.stats[5] = (double)pst[1];
     g.stats[6] = t_sieve;
@@ -489,6 +627,216 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     g.stats[14] = (double)pst[2];
     g.stats[15] = (double)pst[3];
     return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Serving worker
+// ---------------------------------------------------------------------------
+void serve_fail(int rc)
+{
+    Server &v = g.srv;
+    std::lock_guard<std::mutex> lk(v.mu);
+    v.failure = rc;
+    for (auto &kv : v.queries)
+        if (kv.second.state < 2)
+            kv.second.state = 3;
+    v.queued.clear();
+}
+
+// One worker step: admit queued requests as a new batch, run one block of
+// the cyclic sweep for every batch in it, finalize finished queries.
+int serve_step(std::vector<uint64_t> &admit)
+{
+    Server &v = g.srv;
+    hipStream_t s = v.stream;
+    const uint64_t B = g.block_req ? g.block_req : (1ull << 30);
+    if (!admit.empty()) {
+        auto sb = std::make_unique<ServeBatch>();
+        std::vector<uint64_t> ns, us;
+        {
+            std::lock_guard<std::mutex> lk(v.mu);
+            for (uint64_t t : admit)
+                ns.push_back(v.queries[t].n);
+        }
+        for (uint64_t x : ns)
+            us.push_back(g.u_req ? g.u_req : auto_u((long double)x, g.tune.u_scale));
+        RCCHK(sb->b.plan(ns, us, g.tune, s));
+        sb->tickets = admit;
+        sb->open = admit.size();
+        sb->x_entries = sb->b.X;
+        std::lock_guard<std::mutex> lk(v.mu);
+        for (size_t i = 0; i < admit.size(); ++i) {
+            ServeQuery &q = v.queries[admit[i]];
+            q.state = 1;
+            q.idx = (uint32_t)i;
+            q.last_block = sb->b.ymax[i] / B;
+            q.seen = 0;
+            q.seen_map.assign(q.last_block + 1, 0);
+        }
+        v.batches.push_back(std::move(sb));
+    }
+    if (v.batches.empty())
+        return 0;
+
+    // pass length: every block some query in flight still needs
+    uint64_t ymax = 0;
+    {
+        std::lock_guard<std::mutex> lk(v.mu);
+        for (auto &sb : v.batches)
+            for (size_t i = 0; i < sb->tickets.size(); ++i)
+                if (v.queries[sb->tickets[i]].state == 1)
+                    ymax = std::max(ymax, sb->b.ymax[i]);
+    }
+    const uint64_t nb = ymax / B + 1;
+    if (v.cur_block >= nb)
+        v.cur_block = 0;
+    // Blocks are always sieved whole: the pass may grow while it runs, and
+    // the carry into the next block must then cover the whole block.
+    RCCHK(v.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(nb * B), 1024)));
+    RCCHK(v.ss.ensure_pattern());
+    RCCHK(v.ss.ensure_blocks(B));
+    if (v.cur_block == 0)
+        RCCHK(v.ss.reset_carry(s));
+    const uint64_t y1 = v.cur_block * B;
+    const uint64_t y2 = y1 + B - 1;
+    const BlockArgs b = v.ss.make_block(y1, y2);
+    RCCHK(v.ss.sieve(b, s, nullptr));
+    RCCHK(v.ss.scan(b, s));
+    const uint32_t grid = update_grid(g.ncu, g.tune);
+    for (auto &sb : v.batches)
+        if (sb->open)
+            RCCHK(sb->b.update_block(b, grid, s, nullptr));
+
+    // bookkeeping: which queries have now seen every block they need
+    std::vector<std::pair<ServeBatch *, std::vector<uint32_t>>> done;
+    {
+        std::lock_guard<std::mutex> lk(v.mu);
+        for (auto &sb : v.batches) {
+            std::vector<uint32_t> fin;
+            for (size_t i = 0; i < sb->tickets.size(); ++i) {
+                ServeQuery &q = v.queries[sb->tickets[i]];
+                if (q.state != 1)
+                    continue;
+                if (v.cur_block <= q.last_block && !q.seen_map[v.cur_block]) {
+                    q.seen_map[v.cur_block] = 1;
+                    q.seen++;
+                }
+                if (q.seen == q.last_block + 1)
+                    fin.push_back((uint32_t)i);
+            }
+            if (!fin.empty())
+                done.emplace_back(sb.get(), fin);
+        }
+    }
+    v.cur_block++;
+    v.blocks_run++;
+    for (auto &d : done) {
+        ServeBatch *sb = d.first;
+        RCCHK(sb->b.finalize(d.second, s));
+        std::vector<int64_t> out(sb->tickets.size());
+        HIPCHK(hipMemcpyAsync(out.data(), sb->b.out_dev.p, out.size() * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        const double t = now_s();
+        std::lock_guard<std::mutex> lk(v.mu);
+        for (uint32_t i : d.second) {
+            ServeQuery &q = v.queries[sb->tickets[i]];
+            q.result = out[i];
+            q.latency = t - q.t_submit;
+            q.state = 2;
+            sb->open--;
+        }
+    }
+    // retire batches whose queries are all finalized
+    {
+        std::lock_guard<std::mutex> lk(v.mu);
+        for (auto it = v.batches.begin(); it != v.batches.end();) {
+            if ((*it)->open == 0) {
+                v.x_used -= (*it)->x_entries;
+                (*it)->b.release();
+                it = v.batches.erase(it);
+            } else {
+                ++it;
+            }
+        }
+    }
+    v.cv.notify_all();
+    return 0;
+}
+
+void serve_loop()
+{
+    Server &v = g.srv;
+    if (hipSetDevice(g.device) != hipSuccess) {
+        serve_fail(MERTENS_EIO);
+        return;
+    }
+    for (;;) {
+        std::vector<uint64_t> admit;
+        {
+            std::unique_lock<std::mutex> lk(v.mu);
+            v.cv.wait(lk, [&] { return v.stop || !v.queued.empty() || !v.batches.empty(); });
+            if (v.stop)
+                break;
+            // admission by device memory: x entries in flight stay within budget
+            while (!v.queued.empty()) {
+                ServeQuery &q = v.queries[v.queued.front()];
+                const uint64_t u = g.u_req ? g.u_req : auto_u((long double)q.n, g.tune.u_scale);
+                const uint64_t need = std::max<uint64_t>(1, q.n / u);
+                if (v.x_used > 0 && v.x_used + need > g.serve_x_budget)
+                    break;
+                v.x_used += need;
+                admit.push_back(v.queued.front());
+                v.queued.pop_front();
+            }
+        }
+        const int rc = serve_step(admit);
+        if (rc != 0) {
+            serve_fail(rc);
+            std::unique_lock<std::mutex> lk(v.mu);
+            v.cv.notify_all();
+            v.cv.wait(lk, [&] { return v.stop; });
+            break;
+        }
+    }
+    std::lock_guard<std::mutex> lk(v.mu);
+    for (auto &sb : v.batches)
+        sb->b.release();
+    v.batches.clear();
+}
+
+int serve_start()
+{
+    Server &v = g.srv;
+    if (v.running)
+        return 0;
+    HIPCHK(hipStreamCreateWithFlags(&v.stream, hipStreamNonBlocking));
+    v.stop = false;
+    v.failure = 0;
+    v.cur_block = 0;
+    v.x_used = 0;
+    v.running = true;
+    v.worker = std::thread(serve_loop);
+    return 0;
+}
+
+void serve_stop()
+{
+    Server &v = g.srv;
+    if (!v.running)
+        return;
+    {
+        std::lock_guard<std::mutex> lk(v.mu);
+        v.stop = true;
+    }
+    v.cv.notify_all();
+    v.worker.join();
+    (void)hipStreamSynchronize(v.stream);
+    (void)hipStreamDestroy(v.stream);
+    v.stream = nullptr;
+    v.ss.release();
+    v.queries.clear();
+    v.queued.clear();
+    v.running = false;
 }
 
 }  // namespace
@@ -520,9 +868,10 @@ int mertens_init(uint64_t u, uint64_t block)
     g.stream = g.own_stream;
     g.u_req = u;
     g.block_req = block;
-    int rc = upload_pattern();
+    g.tune = Tuning();
+    int rc = g.ss.ensure_pattern();
     if (rc == 0)
-        rc = ensure_primes(1024);
+        rc = g.ss.ensure_primes(1024);
     if (rc != 0) {
         free_all();
         return rc;
@@ -551,10 +900,9 @@ int mertens_query(const uint64_t *n, size_t count, int64_t *out)
             where.push_back(i);
         }
     std::vector<int64_t> res;
-    std::vector<uint64_t> Ls, g0s;
     g.last_valid = false;
     if (!ns.empty()) {
-        int rc = run_query(ns, res, Ls, g0s);
+        int rc = run_query(ns, res);
         if (rc != 0)
             return rc;
     }
@@ -564,8 +912,8 @@ int mertens_query(const uint64_t *n, size_t count, int64_t *out)
         out[i] = 0;
     for (size_t j = 0; j < where.size(); ++j) {
         out[where[j]] = res[j];
-        g.last_L[where[j]] = Ls[j];
-        g.last_g0[where[j]] = g0s[j];
+        g.last_L[where[j]] = g.batch.L[j];
+        g.last_g0[where[j]] = g.batch.g0[j];
     }
     g.last_valid = true;
     return 0;
@@ -584,10 +932,66 @@ int mertens_byproducts(size_t i, int64_t *buf, size_t cap, size_t *len)
         *len = (size_t)L;
     const size_t k = (size_t)std::min<uint64_t>(L, cap);
     if (k > 0) {
-        HIPCHK(hipMemcpyAsync(buf, g.A.as<int64_t>() + g.last_g0[i], k * 8, hipMemcpyDeviceToHost,
-                              g.stream));
+        HIPCHK(hipMemcpyAsync(buf, g.batch.A.as<int64_t>() + g.last_g0[i], k * 8,
+                              hipMemcpyDeviceToHost, g.stream));
         HIPCHK(hipStreamSynchronize(g.stream));
     }
+    return 0;
+}
+
+int mertens_submit(uint64_t n, uint64_t *ticket)
+{
+    if (!ticket)
+        return MERTENS_EINVAL;
+    if (!g.ready)
+        return MERTENS_ENODEV;
+    Server &v = g.srv;
+    if (!v.running)
+        RCCHK(serve_start());
+    std::lock_guard<std::mutex> lk(v.mu);
+    if (v.failure)
+        return v.failure;
+    size_t inflight = 0;
+    for (auto &kv : v.queries)
+        inflight += kv.second.state < 2;
+    if (inflight >= g.serve_capacity)
+        return MERTENS_EAGAIN;
+    const uint64_t t = v.next_ticket++;
+    ServeQuery &q = v.queries[t];
+    q.n = n;
+    q.t_submit = now_s();
+    if (n == 0) {
+        q.state = 2;  // M(0) = 0, nothing to compute
+        q.result = 0;
+    } else {
+        v.queued.push_back(t);
+    }
+    *ticket = t;
+    v.cv.notify_all();
+    return 0;
+}
+
+int mertens_poll(uint64_t ticket, int64_t *out, double *latency_s)
+{
+    if (!g.ready)
+        return MERTENS_ENODEV;
+    Server &v = g.srv;
+    std::lock_guard<std::mutex> lk(v.mu);
+    auto it = v.queries.find(ticket);
+    if (it == v.queries.end())
+        return MERTENS_ERANGE;
+    ServeQuery &q = it->second;
+    if (q.state == 3) {
+        v.queries.erase(it);
+        return v.failure ? v.failure : MERTENS_EIO;
+    }
+    if (q.state != 2)
+        return MERTENS_EINPROGRESS;
+    if (out)
+        *out = q.result;
+    if (latency_s)
+        *latency_s = (q.n == 0) ? 0.0 : q.latency;
+    v.queries.erase(it);
     return 0;
 }
 
@@ -603,26 +1007,44 @@ int mertens_set_param(const char *key, double value)
 {
     if (!key)
         return MERTENS_EINVAL;
-    if (!strcmp(key, "beta")) {
+    if (g.srv.running && strncmp(key, "serve_", 6) != 0) {
+        set_error_text("tuning parameters cannot change while serving");
+        return MERTENS_EINVAL;
+    }
+    if (!strcmp(key, "u_scale")) {
+        if (!(value >= 1e-3 && value <= 1e3))
+            return MERTENS_EINVAL;
+        g.tune.u_scale = value;
+    } else if (!strcmp(key, "beta")) {
         if (!(value > 0.0 && value <= 1.0))
             return MERTENS_EINVAL;
-        g.beta = value;
+        g.tune.beta = value;
     } else if (!strcmp(key, "ychunk")) {
         if (!(value >= 64 && value <= (1 << 24)) || ((uint64_t)value) % 64 != 0)
             return MERTENS_EINVAL;
-        g.ychunk = (uint32_t)value;
+        g.tune.ychunk = (uint32_t)value;
     } else if (!strcmp(key, "kchunk")) {
         if (!(value >= 64 && value <= (1 << 24)))
             return MERTENS_EINVAL;
-        g.kchunk = (uint32_t)value;
+        g.tune.kchunk = (uint32_t)value;
     } else if (!strcmp(key, "klchunk")) {
         if (!(value >= 1 && value <= (1 << 24)))
             return MERTENS_EINVAL;
-        g.klchunk = (uint32_t)value;
+        g.tune.klchunk = (uint32_t)value;
     } else if (!strcmp(key, "waves_per_cu")) {
         if (!(value >= 4 && value <= 64))
             return MERTENS_EINVAL;
-        g.waves_per_cu = (uint32_t)value;
+        g.tune.waves_per_cu = (uint32_t)value;
+    } else if (!strcmp(key, "serve_capacity")) {
+        if (!(value >= 1 && value <= (1 << 20)))
+            return MERTENS_EINVAL;
+        std::lock_guard<std::mutex> lk(g.srv.mu);
+        g.serve_capacity = (size_t)value;
+    } else if (!strcmp(key, "serve_x_budget")) {
+        if (!(value >= 1 && value <= 1e12))
+            return MERTENS_EINVAL;
+        std::lock_guard<std::mutex> lk(g.srv.mu);
+        g.serve_x_budget = (uint64_t)value;
     } else {
         return MERTENS_EINVAL;
     }
@@ -661,7 +1083,13 @@ const char *mertens_strerror(int code)
     }
 }
 
-const char *mertens_last_error(void) { return g_last_error.c_str(); }
+const char *mertens_last_error(void)
+{
+    static thread_local std::string copy;
+    std::lock_guard<std::mutex> lk(g_err_mu);
+    copy = g_last_error;
+    return copy.c_str();
+}
 
 int mertens_debug_div(const uint64_t *n, const uint64_t *d, size_t count, uint64_t *q,
                       int on_device)
@@ -722,9 +1150,9 @@ int mertens_debug_mu(uint64_t y1, size_t count, int8_t *mu, int64_t *mert)
         return MERTENS_ENODEV;
     const uint64_t yend = y1 + count - 1;
     const uint64_t start = y1 - y1 % SEG;
-    RCCHK(ensure_primes(std::max<uint64_t>(ceil_sqrt_host(yend), 1024)));
+    RCCHK(g.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(yend), 1024)));
     const uint64_t B = 1ull << 30;
-    RCCHK(ensure_block_buffers(B));
+    RCCHK(g.ss.ensure_blocks(B));
     DevBuf dmu, dm;
     int rc = ensure(dmu, count);
     if (!rc)
@@ -734,11 +1162,13 @@ int mertens_debug_mu(uint64_t y1, size_t count, int8_t *mu, int64_t *mert)
         dm.release();
         return rc;
     }
-    hipError_t e = launch_zero_u64(reinterpret_cast<uint64_t *>(g.carry.p), 1, g.stream);
+    hipError_t e = hipSuccess;
+    if (g.ss.reset_carry(g.stream) != 0)
+        e = hipErrorUnknown;
     for (uint64_t y = start; e == hipSuccess && y <= yend; y += B) {
         const uint64_t y2 = std::min(y + B - 1, yend);
-        const BlockArgs b = make_block(y, y2);
-        if (sieve_block(b) != 0 || scan_block(b) != 0) {
+        const BlockArgs b = g.ss.make_block(y, y2);
+        if (g.ss.sieve(b, g.stream, nullptr) != 0 || g.ss.scan(b, g.stream) != 0) {
             e = hipErrorUnknown;
             break;
         }

@@ -38,6 +38,8 @@ _sig = {
     "mertens_shutdown": ([], None),
     "mertens_strerror": ([ctypes.c_int], ctypes.c_char_p),
     "mertens_last_error": ([], ctypes.c_char_p),
+    "mertens_submit": ([_u64, _P(_u64)], ctypes.c_int),
+    "mertens_poll": ([_u64, _P(_i64), _P(ctypes.c_double)], ctypes.c_int),
     "mertens_debug_div": ([_P(_u64), _P(_u64), _sz, _P(_u64), ctypes.c_int], ctypes.c_int),
     "mertens_debug_mu": ([_u64, _sz, _P(ctypes.c_int8), _P(_i64)], ctypes.c_int),
 }
@@ -99,6 +101,27 @@ def byproducts(i: int, cap: int | None = None) -> np.ndarray:
     buf = np.zeros(max(cap, 1), dtype=np.int64)
     _check(_lib.mertens_byproducts(i, _i64p(buf), cap, ctypes.byref(n)), "mertens_byproducts")
     return buf[: min(cap, n.value)]
+
+
+def submit(n: int):
+    """Queue M(n) on the serving sweep; returns a ticket, or None if no slot is free."""
+    t = _u64(0)
+    rc = _lib.mertens_submit(n, ctypes.byref(t))
+    if rc == EAGAIN:
+        return None
+    _check(rc, "mertens_submit")
+    return t.value
+
+
+def poll(ticket: int):
+    """(M(n), latency_s) once done, else None."""
+    out = _i64(0)
+    lat = ctypes.c_double(0.0)
+    rc = _lib.mertens_poll(ticket, ctypes.byref(out), ctypes.byref(lat))
+    if rc == EINPROGRESS:
+        return None
+    _check(rc, "mertens_poll")
+    return out.value, lat.value
 
 
 def set_param(key: str, value: float) -> None:
