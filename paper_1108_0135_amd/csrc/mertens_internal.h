@@ -30,8 +30,18 @@ constexpr int TILE = 64;                     // x per tile = one wavefront
 constexpr int UPD_THREADS = 256;             // 4 independent waves per workgroup
 
 // ---------------------------------------------------------------- arguments
-// One y-block [y1, y2] of the sweep; y1 is a multiple of SEG.
+// The per-block values of a y-block [y1, y2] (y1 a multiple of SEG).  The
+// kernels read them from device memory (BlockArgs::bp) so that one captured
+// graph of the block pipeline can be replayed for every block.
+struct BlockParams {
+    uint64_t y1, y2;
+    uint32_t nseg, n_sq, n_sq_lds, pat_off;
+};
+
+// One y-block [y1, y2] of the sweep.  The scalar fields below mirror *bp on
+// the host (for grid sizes); kernels take the values from *bp.
 struct BlockArgs {
+    const BlockParams *bp;
     uint64_t y1, y2;
     uint32_t nseg;
     uint32_t n_small;   // primes with index in [FIRST_SIEVED, n_small) are < SMALL_P
@@ -42,8 +52,9 @@ struct BlockArgs {
     uint2 *pres;              // {p, y1 mod p}: primes >= 5 ascending, residue per block
     uint64_t *res2;           // y1 mod p^2    (per block)
     const uint32_t *pat32;    // pattern bytes as words, length PAT_WORDS
-    uint64_t *masks;          // per 64-y word: {squarefree bits, mu = -1 bits}
-    int64_t *mb;              // per word: M(y) just before the word's first y
+    // per 64-y word, one 32-byte record: {squarefree bits, mu = -1 bits,
+    // M(y) just before the word's first y (int64), unused}
+    uint64_t *words;
     int32_t *seg_sum;         // per segment: sum of mu
     int64_t *seg_off;         // per segment: M(y) just before the segment
     int64_t *carry;           // M(y1 - 1), advanced by the scan kernel
@@ -77,6 +88,11 @@ struct QueryArgs {
 // ---------------------------------------------------------------- launchers
 // All return the hipError_t of the launch (hipGetLastError()).
 hipError_t launch_zero_u64(uint64_t *p, size_t n, hipStream_t s);
+// *cur = p (direct launches)
+hipError_t launch_block_set(const BlockParams &p, BlockParams *cur, hipStream_t s);
+// *cur = table[*index]; ++*index (first node of the captured block graph)
+hipError_t launch_block_next(const BlockParams *table, BlockParams *cur, uint32_t *index,
+                             hipStream_t s);
 hipError_t launch_plan(const QueryArgs &q, hipStream_t s);
 hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s);
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s);

@@ -177,19 +177,61 @@ __device__ inline int64_t wg_exclusive_scan(int64_t v, int64_t *wsum, int64_t &t
 
 // M(y) for y = y1 + off inside the current block: the word's prefix plus the
 // mu values of the word up to and including bit off mod 64.
-__device__ inline int64_t M_at(const uint64_t *__restrict__ masks, const int64_t *__restrict__ mb,
-                               uint64_t off)
+__device__ inline int64_t M_at(const uint64_t *__restrict__ words, uint64_t off)
 {
     const uint64_t w = off >> 6;
     const uint32_t b = (uint32_t)(off & 63);
     const uint64_t lm = (2ull << b) - 1ull;  // bits 0..b (b = 63 wraps to all ones)
-    const uint64_t nz = masks[2 * w], ng = masks[2 * w + 1];
-    return mb[w] + (int64_t)__popcll(nz & lm) - 2 * (int64_t)__popcll(ng & lm);
+    // one 32-byte record: {squarefree bits, mu = -1 bits, M before the word, -}
+    const ulonglong2 m2 = *reinterpret_cast<const ulonglong2 *>(words + 4 * w);
+    const int64_t mb = (int64_t)words[4 * w + 2];
+    return mb + (int64_t)__popcll(m2.x & lm) - 2 * (int64_t)__popcll(m2.y & lm);
+}
+
+// The block's per-block values, taken from device memory.
+__device__ inline BlockArgs load_block(BlockArgs b)
+{
+    const BlockParams p = *b.bp;
+    b.y1 = p.y1;
+    b.y2 = p.y2;
+    b.nseg = p.nseg;
+    b.n_sq = p.n_sq;
+    b.n_sq_lds = p.n_sq_lds;
+    b.pat_off = p.pat_off;
+    return b;
 }
 
 // ====================================================================
 // generic small kernels
 // ====================================================================
+__global__ void k_block_set(BlockParams p, BlockParams *cur)
+{
+    if (threadIdx.x == 0)
+        *cur = p;
+}
+
+hipError_t launch_block_set(const BlockParams &p, BlockParams *cur, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_block_set, dim3(1), dim3(64), 0, s, p, cur);
+    return hipGetLastError();
+}
+
+__global__ void k_block_next(const BlockParams *table, BlockParams *cur, uint32_t *index)
+{
+    if (threadIdx.x == 0) {
+        const uint32_t i = *index;
+        *cur = table[i];
+        *index = i + 1;
+    }
+}
+
+hipError_t launch_block_next(const BlockParams *table, BlockParams *cur, uint32_t *index,
+                             hipStream_t s)
+{
+    hipLaunchKernelGGL(k_block_next, dim3(1), dim3(64), 0, s, table, cur, index);
+    return hipGetLastError();
+}
+
 __global__ void k_zero_u64(uint64_t *p, size_t n)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -267,8 +309,9 @@ __device__ inline uint32_t log_prime(uint32_t p)
 }
 
 // Per block: residues of y1 modulo every sieving prime and square.
-__global__ void k_block_setup(BlockArgs b)
+__global__ void k_block_setup(BlockArgs b_in)
 {
+    const BlockArgs b = load_block(b_in);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.n_sieve)
         return;
@@ -297,10 +340,13 @@ hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s)
 // (A's parity is the number of sieving primes dividing y, as every l_p is
 // odd.)  The result is stored as two 64-bit masks per 64 y.  Squares of
 // primes above SQ_LDS_P are cleared afterwards by k_square_fix.
-__global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b)
+__global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
 {
+    const BlockArgs b = load_block(b_in);
     __shared__ uint32_t lds[SEG / 4];
     const uint32_t seg = blockIdx.x;
+    if (seg >= b.nseg)
+        return;
     const uint32_t tid = threadIdx.x, lane = lane_id();
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     constexpr uint32_t NWAVES = SIEVE_THREADS / 64;
@@ -397,8 +443,7 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b)
             }
         }
         const uint64_t gw = (uint64_t)seg * SEG_WORDS + w;
-        b.masks[2 * gw] = nz;
-        b.masks[2 * gw + 1] = ng;
+        *reinterpret_cast<ulonglong2 *>(b.words + 4 * gw) = make_ulonglong2(nz, ng);
     }
 }
 
@@ -411,8 +456,9 @@ hipError_t launch_sieve(const BlockArgs &b, hipStream_t s)
 // Squares p^2 of primes p > SQ_LDS_P with p^2 <= y2: clear their multiples in
 // [y1, y2] from both masks (mu = 0).  One thread per prime; at most
 // B / 2^20 multiples each.
-__global__ void k_square_fix(BlockArgs b)
+__global__ void k_square_fix(BlockArgs b_in)
 {
+    const BlockArgs b = load_block(b_in);
     const uint32_t i = b.n_sq_lds + blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.n_sq)
         return;
@@ -423,8 +469,8 @@ __global__ void k_square_fix(BlockArgs b)
     for (uint64_t o = r ? p2 - r : 0; o <= span; o += p2) {
         const uint64_t w = o >> 6;
         const unsigned long long keep = ~(1ull << (o & 63));
-        atomicAnd((unsigned long long *)&b.masks[2 * w], keep);
-        atomicAnd((unsigned long long *)&b.masks[2 * w + 1], keep);
+        atomicAnd((unsigned long long *)&b.words[4 * w], keep);
+        atomicAnd((unsigned long long *)&b.words[4 * w + 1], keep);
     }
 }
 
@@ -439,19 +485,22 @@ hipError_t launch_square_fix(const BlockArgs &b, hipStream_t s)
 
 // Per segment: exclusive prefix sums of mu over its mask words (mb, local to
 // the segment) and the segment's total.
-__global__ __launch_bounds__(SIEVE_THREADS) void k_scan_words(BlockArgs b)
+__global__ __launch_bounds__(SIEVE_THREADS) void k_scan_words(BlockArgs b_in)
 {
+    const BlockArgs b = load_block(b_in);
     __shared__ int64_t wsum[SIEVE_THREADS / 64];
     const uint32_t seg = blockIdx.x, tid = threadIdx.x;
+    if (seg >= b.nseg)
+        return;
     const uint64_t gw0 = (uint64_t)seg * SEG_WORDS + tid;
     const uint64_t gw1 = gw0 + SIEVE_THREADS;
-    const int64_t c0 = (int64_t)__popcll(b.masks[2 * gw0]) - 2 * (int64_t)__popcll(b.masks[2 * gw0 + 1]);
-    const int64_t c1 = (int64_t)__popcll(b.masks[2 * gw1]) - 2 * (int64_t)__popcll(b.masks[2 * gw1 + 1]);
+    const int64_t c0 = (int64_t)__popcll(b.words[4 * gw0]) - 2 * (int64_t)__popcll(b.words[4 * gw0 + 1]);
+    const int64_t c1 = (int64_t)__popcll(b.words[4 * gw1]) - 2 * (int64_t)__popcll(b.words[4 * gw1 + 1]);
     int64_t tot0, tot1;
     const int64_t ex0 = wg_exclusive_scan<SIEVE_THREADS>(c0, wsum, tot0);
     const int64_t ex1 = wg_exclusive_scan<SIEVE_THREADS>(c1, wsum, tot1);
-    b.mb[gw0] = ex0;
-    b.mb[gw1] = tot0 + ex1;
+    b.words[4 * gw0 + 2] = (uint64_t)ex0;
+    b.words[4 * gw1 + 2] = (uint64_t)(tot0 + ex1);
     if (tid == 0)
         b.seg_sum[seg] = (int32_t)(tot0 + tot1);
 }
@@ -467,8 +516,9 @@ hipError_t launch_scan_words(const BlockArgs &b, hipStream_t s)
 // ====================================================================
 constexpr int SCAN_THREADS = 1024;
 
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_segments(BlockArgs b)
+__global__ __launch_bounds__(SCAN_THREADS) void k_scan_segments(BlockArgs b_in)
 {
+    const BlockArgs b = load_block(b_in);
     __shared__ int64_t wsum[SCAN_THREADS / 64];
     const uint32_t tid = threadIdx.x;
     const uint32_t per = (b.nseg + SCAN_THREADS - 1) / SCAN_THREADS;
@@ -490,11 +540,12 @@ __global__ __launch_bounds__(SCAN_THREADS) void k_scan_segments(BlockArgs b)
         *b.carry = carry + total;
 }
 
-__global__ void k_fixup(BlockArgs b)
+__global__ void k_fixup(BlockArgs b_in)
 {
+    const BlockArgs b = load_block(b_in);
     const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w < (uint64_t)b.nseg * SEG_WORDS)
-        b.mb[w] += b.seg_off[w / SEG_WORDS];
+        b.words[4 * w + 2] += (uint64_t)b.seg_off[w / SEG_WORDS];
 }
 
 hipError_t launch_scan_segments(const BlockArgs &b, hipStream_t s)
@@ -516,8 +567,9 @@ hipError_t launch_fixup(const BlockArgs &b, hipStream_t s)
 // Prep: per x, the k range whose quotients floor(m/k) land in [y1, y2]; the
 // one-off term -K*M(Y) when Y is in this block; per tile, the number of
 // work items of the run-length part and of the explicit k part.
-__global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockArgs b)
+__global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockArgs b_in)
 {
+    const BlockArgs b = load_block(b_in);
     const uint32_t tile =
         __builtin_amdgcn_readfirstlane(blockIdx.x * (UPD_THREADS / 64) + (threadIdx.x >> 6));
     const uint32_t lane = lane_id();
@@ -544,7 +596,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockA
         q.x_klo[g] = klo;
         q.x_khi[g] = khi;
         if (Y >= y1e && Y <= b.y2)
-            q.S[g] -= K * (uint64_t)M_at(b.masks, b.mb, Y - b.y1);
+            q.S[g] -= K * (uint64_t)M_at(b.words, Y - b.y1);
     }
     const bool has = klo <= khi;
     const uint64_t kpairs = wave_sum_u64(has ? khi - klo + 1 : 0ull);
@@ -691,8 +743,8 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
     double accf = 0.0;  // integer-valued, |accf| < ychunk * 2^32 < 2^53
     for (uint64_t wbase = cs & ~63ull; wbase <= ce; wbase += 64) {
         const uint64_t woff = (wbase - b.y1) >> 6;
-        const uint64_t nz = uniform_u64(b.masks[2 * woff]);
-        const uint64_t ng = uniform_u64(b.masks[2 * woff + 1]);
+        const uint64_t nz = uniform_u64(b.words[4 * woff]);
+        const uint64_t ng = uniform_u64(b.words[4 * woff + 1]);
         const uint32_t lob = wbase < cs ? (uint32_t)(cs - wbase) : 0u;
         const uint32_t hib = (ce - wbase) < 63 ? (uint32_t)(ce - wbase) : 63u;
         uint64_t bits = nz & (~0ull << lob) & ((2ull << hib) - 1ull);
@@ -819,7 +871,7 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
                         uint64_t y = (uint32_t)t;
                         if (fabs(qd - t - 0.5) > 0.5 - QEPS)
                             y = fix_quotient(m, k, t);
-                        acc += (uint64_t)M_at(b.masks, b.mb, y - b.y1);
+                        acc += (uint64_t)M_at(b.words, y - b.y1);
                     }
                 }
             } else {
@@ -833,7 +885,7 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
                     const uint32_t s2 = __builtin_amdgcn_readlane(sh2, j);
                     if (k >= klo && k <= khi) {
                         const uint64_t y = gm_div(m, mg, s1, s2);
-                        acc += (uint64_t)M_at(b.masks, b.mb, y - b.y1);
+                        acc += (uint64_t)M_at(b.words, y - b.y1);
                     }
                 }
             }
@@ -846,7 +898,7 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
             ke = khi;
         for (uint64_t k = ks; k <= ke && klo <= khi; ++k) {
             const uint64_t y = div_fp_exact(m, k);
-            acc += (uint64_t)M_at(b.masks, b.mb, y - b.y1);
+            acc += (uint64_t)M_at(b.words, y - b.y1);
         }
     }
     if (valid)
@@ -855,8 +907,9 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
 
 // Persistent update kernel of one block: every wave takes work items from
 // a device counter until the block's items are exhausted.
-__global__ __launch_bounds__(UPD_THREADS) void k_update(QueryArgs q, BlockArgs b)
+__global__ __launch_bounds__(UPD_THREADS) void k_update(QueryArgs q, BlockArgs b_in)
 {
+    const BlockArgs b = load_block(b_in);
     const uint32_t lane = lane_id();
     const uint64_t total = uniform_u64(q.tile_items[q.ntiles]);
     for (;;) {
@@ -1008,18 +1061,19 @@ hipError_t launch_debug_div(const uint64_t *n, const uint64_t *d, uint64_t *q, s
 }
 
 // mu(y) and M(y) (relative to the block's carry) for y in [y_first, y_first+count)
-__global__ void k_debug_mu(BlockArgs b, uint64_t y_first, uint32_t count, int8_t *mu, int64_t *mert)
+__global__ void k_debug_mu(BlockArgs b_in, uint64_t y_first, uint32_t count, int8_t *mu, int64_t *mert)
 {
+    const BlockArgs b = load_block(b_in);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= count)
         return;
     const uint64_t off = y_first + i - b.y1;
     const uint64_t w = off >> 6;
     const uint32_t bt = (uint32_t)(off & 63);
-    const uint64_t nz = b.masks[2 * w], ng = b.masks[2 * w + 1];
+    const uint64_t nz = b.words[4 * w], ng = b.words[4 * w + 1];
     mu[i] = ((nz >> bt) & 1) ? (((ng >> bt) & 1) ? -1 : 1) : 0;
     if (mert)
-        mert[i] = M_at(b.masks, b.mb, off);
+        mert[i] = M_at(b.words, off);
 }
 
 hipError_t launch_debug_mu(const BlockArgs &b, uint64_t y_first, uint32_t count, int8_t *mu,

@@ -144,6 +144,7 @@ struct Tuning {
     double u_scale = 1.0;  // automatic u = u_scale * (sum of the batch's n)^(2/3)
     double beta = 0.2;
     uint32_t ychunk = 4096, kchunk = 2048, klchunk = 256, waves_per_cu = 16;
+    bool graph = false;  // replay one captured hipGraph per block
 };
 
 // ---------------------------------------------------------------------------
@@ -152,12 +153,13 @@ struct Tuning {
 struct SieveState {
     uint64_t psieve = 0;
     std::vector<uint32_t> h_primes;  // primes >= 5 up to psieve
-    DevBuf pres, res2, pattern, masks, mb, seg_sum, seg_off, carry;
+    DevBuf pres, res2, pattern, words, seg_sum, seg_off, carry, bp_cur, bp_table, bp_index;
     bool have_pattern = false;
 
     void release()
     {
-        DevBuf *bufs[] = {&pres, &res2, &pattern, &masks, &mb, &seg_sum, &seg_off, &carry};
+        DevBuf *bufs[] = {&pres, &res2, &pattern, &words, &seg_sum, &seg_off, &carry,
+                          &bp_cur, &bp_table, &bp_index};
         for (DevBuf *b : bufs)
             b->release();
         h_primes.clear();
@@ -219,11 +221,12 @@ struct SieveState {
 
     int ensure_blocks(uint64_t B)
     {
-        RCCHK(ensure(masks, B / 64 * 16));
-        RCCHK(ensure(mb, B / 64 * 8));
+        RCCHK(ensure(words, B / 64 * 32));
         RCCHK(ensure(seg_sum, B / SEG * 4));
         RCCHK(ensure(seg_off, B / SEG * 8));
         RCCHK(ensure(carry, 64));
+        RCCHK(ensure(bp_cur, sizeof(BlockParams)));
+        RCCHK(ensure(bp_index, 64));
         return 0;
     }
 
@@ -237,6 +240,7 @@ struct SieveState {
     BlockArgs make_block(uint64_t y1, uint64_t y2) const
     {
         BlockArgs b;
+        b.bp = bp_cur.as<BlockParams>();
         b.y1 = y1;
         b.y2 = y2;
         b.nseg = (uint32_t)((y2 - y1) / SEG + 1);
@@ -248,18 +252,43 @@ struct SieveState {
         b.pres = pres.as<uint2>();
         b.res2 = res2.as<uint64_t>();
         b.pat32 = pattern.as<uint32_t>();
-        b.masks = masks.as<uint64_t>();
-        b.mb = mb.as<int64_t>();
+        b.words = words.as<uint64_t>();
         b.seg_sum = seg_sum.as<int32_t>();
         b.seg_off = seg_off.as<int64_t>();
         b.carry = carry.as<int64_t>();
         return b;
     }
 
-    // residues, then the sieve (an event may be recorded in between so the
-    // sieve kernels are timed alone), then the large-square fix
-    int sieve(const BlockArgs &b, hipStream_t s, hipEvent_t between) const
+    static BlockParams params_of(const BlockArgs &b)
     {
+        BlockParams p;
+        p.y1 = b.y1;
+        p.y2 = b.y2;
+        p.nseg = b.nseg;
+        p.n_sq = b.n_sq;
+        p.n_sq_lds = b.n_sq_lds;
+        p.pat_off = b.pat_off;
+        return p;
+    }
+
+    // Grid sizes that cover any block of length B (for the captured graph;
+    // the kernels take the true values from the device parameters).
+    BlockArgs max_block(uint64_t B) const
+    {
+        BlockArgs b = make_block(0, B - 1);
+        b.nseg = (uint32_t)(B / SEG);
+        b.n_sq_lds = 0;
+        b.n_sq = (uint32_t)h_primes.size();
+        return b;
+    }
+
+    // block parameters, residues, then the sieve (an event may be recorded
+    // before it so the sieve kernels are timed alone), then the large-square
+    // fix.  set_params = false when a graph node loads the parameters.
+    int sieve(const BlockArgs &b, hipStream_t s, hipEvent_t between, bool set_params = true) const
+    {
+        if (set_params)
+            HIPCHK(launch_block_set(params_of(b), bp_cur.as<BlockParams>(), s));
         HIPCHK(launch_block_setup(b, s));
         if (between)
             HIPCHK(hipEventRecord(between, s));
@@ -581,7 +610,45 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
     RCCHK(g.ss.reset_carry(s));
     std::vector<size_t> marks;
     marks.reserve(nblocks);
-    for (uint64_t bi = 0; bi < nblocks; ++bi) {
+    if (g.tune.graph) {
+        // one captured graph of the whole block pipeline, replayed per block;
+        // its first node loads the block's parameters from a table
+        std::vector<BlockParams> tab(nblocks);
+        for (uint64_t bi = 0; bi < nblocks; ++bi)
+            tab[bi] = SieveState::params_of(
+                g.ss.make_block(bi * B, std::min(bi * B + B - 1, ymax)));
+        RCCHK(ensure(g.ss.bp_table, nblocks * sizeof(BlockParams)));
+        HIPCHK(hipMemcpyAsync(g.ss.bp_table.p, tab.data(), nblocks * sizeof(BlockParams),
+                              hipMemcpyHostToDevice, s));
+        HIPCHK(launch_zero_u64(g.ss.bp_index.as<uint64_t>(), 1, s));
+        HIPCHK(hipStreamSynchronize(s));  // the host table goes out of scope
+        const BlockArgs bm = g.ss.max_block(B);
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        int rc = 0;
+        if (launch_block_next(g.ss.bp_table.as<BlockParams>(), g.ss.bp_cur.as<BlockParams>(),
+                              g.ss.bp_index.as<uint32_t>(), s) != hipSuccess)
+            rc = MERTENS_EIO;
+        if (!rc)
+            rc = g.ss.sieve(bm, s, nullptr, false);
+        if (!rc)
+            rc = g.ss.scan(bm, s);
+        if (!rc)
+            rc = bt.update_block(bm, grid, s, nullptr);
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (rc)
+            return rc;
+        HIPCHK(ec);
+        HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        hipError_t el = hipSuccess;
+        for (uint64_t bi = 0; bi < nblocks && el == hipSuccess; ++bi)
+            el = hipGraphLaunch(exec, s);
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(el);
+    }
+    for (uint64_t bi = 0; bi < nblocks && !g.tune.graph; ++bi) {
         const uint64_t y1 = bi * B;
         const uint64_t y2 = std::min(y1 + B - 1, ymax);
         const BlockArgs b = g.ss.make_block(y1, y2);
@@ -1015,6 +1082,10 @@ int mertens_set_param(const char *key, double value)
         if (!(value >= 1e-3 && value <= 1e3))
             return MERTENS_EINVAL;
         g.tune.u_scale = value;
+    } else if (!strcmp(key, "graph")) {
+        if (!(value == 0.0 || value == 1.0))
+            return MERTENS_EINVAL;
+        g.tune.graph = value != 0.0;
     } else if (!strcmp(key, "beta")) {
         if (!(value > 0.0 && value <= 1.0))
             return MERTENS_EINVAL;

@@ -173,3 +173,17 @@ def test_section6_extreme(mt):
     # Section 6: M(11609864264058592345) = -1,995,900,927
     _reinit(mt)
     assert int(mt.query([inputs.EXTREME_N])[0]) == inputs.EXTREME_M
+
+
+def test_graph_replays_match_eager(mt):
+    # the captured block pipeline, replayed once per block, against direct
+    # launches; eager queries run between the graph runs
+    g = GOLDEN["n1e12"]
+    for rep in range(3):
+        _reinit(mt, u=10**8, block=1 << 22, graph=1)
+        assert int(mt.query([g["n"]])[0]) == g["M"]
+        assert list(mt.byproducts(0)) == g["byproducts"]
+        mt.set_param("graph", 0)
+        assert list(mt.query(GOLDEN["batch48"]["n"][:8])) == GOLDEN["batch48"]["M"][:8]
+    _reinit(mt, u=5 * 10**10, block=1 << 30, graph=1)
+    assert int(mt.query([10**16])[0]) == inputs.TABLE1[10**16]
