@@ -37,9 +37,10 @@ METRIC = "sieved y/sec through update; batched vs plain M(n) queries/sec, 1 GPU,
 HBM_PEAK_GBS = 8000.0
 CU, CLOCK_GHZ, LANES = 256, 2.4, 64
 INT_VALU_PEAK_TOPS = CU * LANES * CLOCK_GHZ / 1000.0  # 39.3 T int32 lane-ops/s
-# algorithmic cost of one quotient floor(m/d) by an invariant divisor plus its
-# accumulation, in full-rate int32 lane-op equivalents
-OPS_PER_QUOTIENT = 24
+# algorithmic cost of one exact quotient floor(m/d) with its accumulation, in
+# full-rate VALU lane-ops: estimate (fp64 multiply), truncate, residual (fma),
+# near-integer offset and test (add, compare), accumulate (add) -- see the design doc
+OPS_PER_QUOTIENT = 6
 
 
 def cpu_baseline(budget_s: float = 15.0) -> dict:
@@ -240,6 +241,9 @@ def main() -> int:
               "(DESIGN.md describes how the sweep would shard)", file=sys.stderr)
         return 2
 
+    # torch first: it and the library share the HIP runtime library, and
+    # torch must be the one that loads it
+    import torch  # noqa: F401
     from paper_1108_0135_amd import mertens as mt
     try:
         if args.workload == "default":
