@@ -225,12 +225,30 @@ def workload_serving(args, mt) -> dict:
                            "p99_s": p(fifo_lat, 99)}}
 
 
+def workload_copy(args, mt) -> dict:
+    """A plain device copy of known size (calibrates HBM byte counters)."""
+    import torch
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+    a.fill_(1)
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    return {"workload": "copy", "bytes_read": nbytes, "bytes_written": nbytes,
+            "GBps": 2 * nbytes / dt / 1e9}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["default", "batched", "serving"], default="default")
+    ap.add_argument("--workload", choices=["default", "batched", "serving", "copy"],
+                    default="default")
     ap.add_argument("--rate", type=float, default=10.0)
     ap.add_argument("--count", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -252,6 +270,8 @@ def main() -> int:
                 line["cpu_baseline"] = cpu_baseline()
         elif args.workload == "batched":
             line = workload_batched(args, mt)
+        elif args.workload == "copy":
+            line = workload_copy(args, mt)
         else:
             line = workload_serving(args, mt)
     except RuntimeError as e:

@@ -133,6 +133,7 @@ int mertens_set_stream(void *hip_stream);
  *                 y <= Y and the explicit k part (K = floor(beta*sqrt(m))),
  *                 in (0, 1]; default 0.2
  *   "ychunk"      y per work item of the run-length part, multiple of 64
+ *                 in [64, 2^20] (default 4096)
  *   "kchunk"      k per work item of the explicit k part
  *   "waves_per_cu" persistent update grid size per compute unit
  *   "serve_capacity"  most requests in flight for mertens_submit (4096)

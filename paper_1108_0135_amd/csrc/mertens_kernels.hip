@@ -709,13 +709,183 @@ __device__ inline uint64_t fix_quotient(uint64_t m, uint64_t d, double t)
     return qv;
 }
 
+constexpr int RL_XS = 16;
+constexpr uint32_t RL_ENT_SPAN = 4096;  // y per compacted sub-chunk
+constexpr uint32_t RL_ENT_CAP = 3072;   // 1024 of any 4096 consecutive y are multiples of 4
+
+// One pass of RL_XS x (m as fp64 in mf, NaN past the tile's end) over the
+// compacted entries.  Per pair: qh = m/y - 1/2 rounded once (fma),
+// t = rint(qh) is floor(m/y) unless qh lies within QEPS of a half-integer,
+// which the running max of |qh - t| detects; such entries redo the RL_XS
+// pairs with the integer fix-up.  With CHECK, pairs with y > Y_x are skipped
+// (sub-chunks that straddle some x's Y); *cnt counts the pairs taken.
+template <bool CHECK>
+__device__ inline void rl_pass(const uint16_t *ent, uint32_t total, uint32_t wb0,
+                               const double (&mf)[RL_XS], const uint32_t (&Yv)[RL_XS],
+                               const uint64_t *xm, double (&acc)[RL_XS], uint32_t *cnt)
+{
+    const uint32_t lane = lane_id();
+    for (uint32_t t = lane; t < total; t += 64) {
+        const uint32_t e = ent[t];
+        const uint32_t y = wb0 + (e & 0x0FFFu);
+        const double sg = (e & 0x8000u) ? -1.0 : 1.0;
+        const double r = 1.0 / (double)y;
+        double dmax = 0.0;
+#pragma unroll
+        for (int i = 0; i < RL_XS; ++i) {
+            if (CHECK && y > Yv[i])
+                continue;
+            const double qh = fma(mf[i], r, -0.5);
+            const double tq = rint(qh);
+            acc[i] = fma(sg, tq, acc[i]);
+            dmax = fmax(dmax, fabs(qh - tq));
+            if (CHECK)
+                *cnt += 1;
+        }
+        if (dmax > 0.5 - QEPS) {
+            // opaque copy: recompute here rather than keep RL_XS values live
+            double r2 = r;
+            __asm__ volatile("" : "+v"(r2));
+#pragma unroll
+            for (int i = 0; i < RL_XS; ++i) {
+                if (CHECK && y > Yv[i])
+                    continue;
+                const double qh = fma(mf[i], r2, -0.5);
+                const double tq = rint(qh);
+                if (fabs(qh - tq) > 0.5 - QEPS) {
+                    const uint64_t exact = fix_quotient(xm[i], y, tq);
+                    acc[i] = fma(sg, (double)(int64_t)(exact - (uint64_t)tq), acc[i]);
+                }
+            }
+        }
+    }
+}
+
+// Sum of each of RL_XS = 16 values over the wave, by halving exchanges:
+// after the xor-32/16/8/4 steps lane l holds a partial sum of value
+// (l >> 2) only, and the xor-2/1 steps complete it on all four lanes of
+// each quad (17 exchanges instead of 16 full reductions).
+__device__ inline double wave_multi_sum16(double (&a)[RL_XS])
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int h = 8; h >= 1; h >>= 1) {
+        const int o = h * 4;  // 32, 16, 8, 4
+        const bool up = (lane & (uint32_t)o) != 0;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const double send = up ? a[j] : a[j + h];
+            const double keep = up ? a[j + h] : a[j];
+            a[j] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    double v = a[0];
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 1, 64);
+    return v;
+}
+
+// Run-length part, lanes over y.  The item's y range is taken in sub-chunks
+// of 4096 aligned y: the squarefree y of a sub-chunk are compacted into LDS
+// (12-bit offset | sign << 15) and each lane takes every 64th entry against
+// RL_XS x of the tile at a time (m_x uniform), i.e. RL_XS independent
+// quotient chains per lane and entry.  Per-x sums stay in registers (lane l
+// holds x (l >> 2) + 16 (l & 3)) and leave with one 64-lane atomic per
+// item.  Requires every quotient below 2^32 (y > m/2^32 for every x of the
+// tile) and y < 2^32.
+__device__ inline void mu_item_lanes(const QueryArgs &q, const BlockArgs &b, uint32_t tile,
+                                     uint64_t cs, uint64_t ce, uint16_t *ent)
+{
+    const uint32_t lane = lane_id();
+    const uint32_t nx = __builtin_amdgcn_readfirstlane(q.tile_nx[tile]);
+    const uint64_t g0 = uniform_u64(q.tile_g0[tile]);
+    // lane l sums x (l >> 2) + 16 (l & 3) of the tile
+    const uint32_t qd = lane & 3u, xi = (lane >> 2) + 16u * qd;
+    double mine = 0.0;
+    uint64_t nq = 0;
+    for (uint64_t sb = cs & ~63ull; sb <= ce; sb += RL_ENT_SPAN) {
+        const uint64_t ss = sb > cs ? sb : cs;
+        const uint64_t se = (ce - sb) < RL_ENT_SPAN - 1 ? ce : sb + RL_ENT_SPAN - 1;
+        const uint32_t nw = (uint32_t)((se - sb) >> 6) + 1;  // <= 64
+        uint64_t bits = 0, ngw = 0;
+        if (lane < nw) {
+            const uint64_t wbase = sb + 64ull * lane;
+            const ulonglong2 m2 =
+                *reinterpret_cast<const ulonglong2 *>(b.words + 4 * ((wbase - b.y1) >> 6));
+            const uint32_t lob = wbase < ss ? (uint32_t)(ss - wbase) : 0u;
+            const uint32_t hib = (se - wbase) < 63 ? (uint32_t)(se - wbase) : 63u;
+            bits = m2.x & (~0ull << lob) & ((2ull << hib) - 1ull);
+            ngw = m2.y;
+        }
+        const uint32_t cnt = (uint32_t)__popcll(bits);
+        uint32_t incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t t = __shfl_up(incl, o, 64);
+            if (lane >= (uint32_t)o)
+                incl += t;
+        }
+        const uint32_t total = __builtin_amdgcn_readlane(incl, 63);
+        // the previous sub-chunk's readers are done with ent
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        uint32_t pos = incl - cnt;
+        while (bits) {
+            const uint32_t bt = (uint32_t)__builtin_ctzll(bits);
+            bits &= bits - 1;
+            ent[pos++] = (uint16_t)((lane * 64 + bt) | (uint32_t)(((ngw >> bt) & 1ull) << 15));
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+
+#pragma unroll 1
+        for (uint32_t p = 0; p < 4; ++p) {
+            const uint32_t xs = p * RL_XS;
+            if (xs >= nx)
+                break;
+            const uint32_t nxs = (nx - xs) < (uint32_t)RL_XS ? nx - xs : (uint32_t)RL_XS;
+            double mf[RL_XS], acc[RL_XS];
+            uint32_t Yv[RL_XS];
+            uint32_t ymin = ~0u;
+#pragma unroll
+            for (int i = 0; i < RL_XS; ++i) {
+                const bool ok = (uint32_t)i < nxs;
+                const uint64_t mi = ok ? uniform_u64(q.x_m[g0 + xs + i]) : 0;
+                Yv[i] = ok ? (uint32_t)uniform_u64(q.x_Y[g0 + xs + i]) : 0u;
+                // NaN past the tile's end: never near a half-integer, never summed
+                mf[i] = ok ? (double)mi : __longlong_as_double(0x7ff8000000000000ll);
+                acc[i] = 0.0;
+                if (ok && Yv[i] < ymin)
+                    ymin = Yv[i];
+            }
+            if (se > ymin) {  // some y of the sub-chunk exceeds some x's Y
+                uint32_t c = 0;
+                rl_pass<true>(ent, total, (uint32_t)sb, mf, Yv, q.x_m + g0 + xs, acc, &c);
+                nq += c;
+            } else {
+                rl_pass<false>(ent, total, (uint32_t)sb, mf, Yv, q.x_m + g0 + xs, acc, nullptr);
+                nq += lane == 0 ? (uint64_t)total * nxs : 0;
+            }
+            // NaN sums of absent x stay on lanes that never write them
+            const double v = wave_multi_sum16(acc);
+            if (qd == p)
+                mine += v;
+        }
+    }
+    if (xi < nx)
+        atomicAdd((unsigned long long *)&q.S[g0 + xi], (unsigned long long)(int64_t)mine);
+    nq = wave_sum_u64(nq);
+    if (lane == 0)
+        atomicAdd((unsigned long long *)&q.pair_stats[2], (unsigned long long)nq);
+}
+
 // Run-length part of one (tile, y-chunk) item:
 //   S[x] += sum_{y in chunk, y <= Y_x, mu(y) != 0} mu(y) floor(m_x / y).
 // y is uniform across the wave (lane = x): the mask words come from scalar
 // loads, and per 64-y word each lane computes one divisor's constants (1/y
 // for the fp64 path, the Granlund-Montgomery multiplier for the integer
 // path), which readlane broadcasts.
-__device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t tile, uint64_t c)
+__device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t tile, uint64_t c,
+                               uint16_t *ent)
 {
     const uint32_t lane = lane_id();
     const uint32_t nx = q.tile_nx[tile];
@@ -739,8 +909,12 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
         ce = yb_t;
     if (cs < y1e)
         cs = y1e;
+    if (ent && cs > qbig && cs <= ce && ce < (1ull << 32)) {
+        mu_item_lanes(q, b, tile, cs, ce, ent);
+        return;
+    }
     uint64_t acc = 0, nq = 0;
-    double accf = 0.0;  // integer-valued, |accf| < ychunk * 2^32 < 2^53
+    double accf = 0.0;  // integer-valued, |accf| < ychunk * 2^32 <= 2^52
     for (uint64_t wbase = cs & ~63ull; wbase <= ce; wbase += 64) {
         const uint64_t woff = (wbase - b.y1) >> 6;
         const uint64_t nz = uniform_u64(b.words[4 * woff]);
@@ -907,10 +1081,12 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
 
 // Persistent update kernel of one block: every wave takes work items from
 // a device counter until the block's items are exhausted.
-__global__ __launch_bounds__(UPD_THREADS) void k_update(QueryArgs q, BlockArgs b_in)
+__global__ __launch_bounds__(UPD_THREADS, 4) void k_update(QueryArgs q, BlockArgs b_in)
 {
+    __shared__ uint16_t ent_lds[UPD_THREADS / 64][RL_ENT_CAP];
     const BlockArgs b = load_block(b_in);
     const uint32_t lane = lane_id();
+    uint16_t *ent = ent_lds[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
     const uint64_t total = uniform_u64(q.tile_items[q.ntiles]);
     for (;;) {
         // One ticket per wave.  Every lane executes the atomic (lane 0 adds
@@ -927,7 +1103,7 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update(QueryArgs q, BlockArgs b
         const uint64_t local = uniform_u64(item - q.tile_items[tile]);
         const uint32_t nmu = __builtin_amdgcn_readfirstlane(q.tile_nmu[tile]);
         if (local < nmu)
-            mu_item(q, b, tile, local);
+            mu_item(q, b, tile, local, ent);
         else
             k_item(q, b, tile, local - nmu);
     }

@@ -1091,7 +1091,8 @@ int mertens_set_param(const char *key, double value)
             return MERTENS_EINVAL;
         g.tune.beta = value;
     } else if (!strcmp(key, "ychunk")) {
-        if (!(value >= 64 && value <= (1 << 24)) || ((uint64_t)value) % 64 != 0)
+        // partial sums of a work item stay below ychunk * 2^32 <= 2^52: exact in fp64
+        if (!(value >= 64 && value <= (1 << 20)) || ((uint64_t)value) % 64 != 0)
             return MERTENS_EINVAL;
         g.tune.ychunk = (uint32_t)value;
     } else if (!strcmp(key, "kchunk")) {

@@ -38,6 +38,7 @@ def test_bad_arguments_without_gpu():
     assert lib.mertens_set_param(b"nope", 1.0) == mt.EINVAL
     assert lib.mertens_set_param(b"beta", 0.0) == mt.EINVAL
     assert lib.mertens_set_param(b"ychunk", 100.0) == mt.EINVAL  # not a multiple of 64
+    assert lib.mertens_set_param(b"ychunk", float(1 << 21)) == mt.EINVAL  # fp64 sums inexact
     # divisor outside [1, 2^32)
     n = np.array([5], dtype=np.uint64)
     for bad in (0, 1 << 32):
