@@ -39,7 +39,7 @@ CU, CLOCK_GHZ, LANES = 256, 2.4, 64
 INT_VALU_PEAK_TOPS = CU * LANES * CLOCK_GHZ / 1000.0  # 39.3 T int32 lane-ops/s
 # algorithmic cost of one exact quotient floor(m/d) with its accumulation, in
 # full-rate VALU lane-ops: estimate (fp64 multiply), truncate, residual (fma),
-# near-integer offset and test (add, compare), accumulate (add) -- see the design doc
+# near-integer offset and test (add, compare), accumulate (add)
 OPS_PER_QUOTIENT = 6
 
 
@@ -255,8 +255,8 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(DESIGN.md describes how the sweep would shard)", file=sys.stderr)
+        print("bench.py runs on one GPU only: the sweep has no multi-GPU path",
+              file=sys.stderr)
         return 2
 
     # torch first: it and the library share the HIP runtime library, and

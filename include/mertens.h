@@ -148,7 +148,8 @@ int mertens_set_param(const char *key, double value);
  * Writes up to cap doubles into vals in this order (returns how many):
  *   0 sieved y (Ymax+1)   1 blocks         2 u used        3 sum of L
  *   4 sum over x of Y (run-length range)  5 sum over x of explicit k terms
- *   6 ms sieve kernels    7 ms scan+fixup  8 ms update prep  9 ms update
+ *   6 ms sieve kernels (with the fused M(y) prefix)
+ *   7 ms separate scan passes (none: always 0)  8 ms update prep  9 ms update
  *  10 ms finalize         11 ms total device time          12 update launches
  *  13 sieve launches      14 run-length quotients taken (mu(y) != 0, y <= Y)
  *  15 explicit k quotients taken (= M(y) gathers)

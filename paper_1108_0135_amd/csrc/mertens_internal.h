@@ -20,8 +20,8 @@ constexpr uint32_t PAT_WORDS = (PAT + SEG) / 4 + 16;
 // a whole wavefront, lane i taking the i-th multiple; larger ones by one lane.
 constexpr uint32_t SMALL_P = SEG / 64;
 // Squares of primes up to this bound are flagged in LDS by whole wavefronts;
-// larger squares (at most 2^31 / 2^20 multiples per block each) are cleared
-// from the finished masks by a separate kernel.
+// a larger square (> 2^20 > SEG) meets a segment at most once and is placed
+// by one lane per prime.
 constexpr uint32_t SQ_LDS_P = 1024;
 // First index of the prime table that is sieved (table starts at 5; the
 // pattern covers 5, 7, 11, 13, so sieving starts at 17 = index 4).
@@ -55,9 +55,11 @@ struct BlockArgs {
     // per 64-y word, one 32-byte record: {squarefree bits, mu = -1 bits,
     // M(y) just before the word's first y (int64), unused}
     uint64_t *words;
-    int32_t *seg_sum;         // per segment: sum of mu
-    int64_t *seg_off;         // per segment: M(y) just before the segment
-    int64_t *carry;           // M(y1 - 1), advanced by the scan kernel
+    // per segment: look-back state of the fused prefix scan, 2-bit flag
+    // (1 = segment total, 2 = M(y) at the segment's end) over a 62-bit value
+    uint64_t *seg_state;
+    uint32_t *seg_ticket;     // segments are claimed in ticket order
+    int64_t *carry;           // M(y1 - 1), advanced by the block's last segment
 };
 
 // The per-query state of one sweep (a batch of queries sharing the sieve).
@@ -69,7 +71,14 @@ struct QueryArgs {
     uint64_t *S;                        // wrapping uint64 contribution sums
     int64_t *A;                         // final M(floor(n/x))
     uint64_t *x_klo, *x_khi;            // k range of the current block
-    // tiles: 64 consecutive x of one query
+    // Queries with equal L form one keyed group when there are several:
+    // its entries are the distinct pairs (x, m = floor(n_i/x)) over the
+    // group's n_i, sorted by x then m (S and A depend on x and m only).
+    const uint32_t *key_x;    // per entry of a keyed group: x
+    const uint32_t *key_off;  // per group, x = 1..L+1: first entry of x (from the group's g0)
+    const uint64_t *q_koff;   // per query: its group's base in key_off, or ~0 (plain query)
+    // tiles: 64 consecutive x of one plain query (tile_x0 >= 1) or 64
+    // consecutive entries of a keyed group (tile_x0 = 0)
     uint32_t ntiles;
     const uint32_t *tile_q, *tile_x0, *tile_nx;
     const uint64_t *tile_g0;
@@ -96,10 +105,6 @@ hipError_t launch_block_next(const BlockParams *table, BlockParams *cur, uint32_
 hipError_t launch_plan(const QueryArgs &q, hipStream_t s);
 hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s);
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s);
-hipError_t launch_square_fix(const BlockArgs &b, hipStream_t s);
-hipError_t launch_scan_words(const BlockArgs &b, hipStream_t s);
-hipError_t launch_scan_segments(const BlockArgs &b, hipStream_t s);
-hipError_t launch_fixup(const BlockArgs &b, hipStream_t s);
 hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
 hipError_t launch_scan_items(const QueryArgs &q, hipStream_t s);
 hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, hipStream_t s);
@@ -107,6 +112,9 @@ hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, 
 hipError_t launch_finalize(const QueryArgs &q, const uint32_t *qlist, uint32_t count,
                            hipStream_t s);
 hipError_t launch_collect(const QueryArgs &q, int64_t *out, hipStream_t s);
+// out[c-1] = A entry of (c, floor(n_qi/c)) for c = 1..count (keyed group member qi)
+hipError_t launch_keyed_byproducts(const QueryArgs &q, uint32_t qi, uint64_t count, int64_t *out,
+                                   hipStream_t s);
 hipError_t launch_debug_div(const uint64_t *n, const uint64_t *d, uint64_t *q, size_t count,
                             hipStream_t s);
 hipError_t launch_debug_mu(const BlockArgs &b, uint64_t y_first, uint32_t count, int8_t *mu,

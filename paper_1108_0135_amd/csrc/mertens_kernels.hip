@@ -260,13 +260,15 @@ __global__ __launch_bounds__(UPD_THREADS) void k_plan(QueryArgs q)
         return;
     const uint32_t qi = q.tile_q[tile];
     const uint32_t nx = q.tile_nx[tile];
+    const uint32_t x0 = q.tile_x0[tile];
     const bool valid = lane < nx;
     uint64_t Y = 0, ysum = 0, ksum = 0;
     if (valid) {
         const uint64_t g = q.tile_g0[tile] + lane;
-        const uint64_t x = (uint64_t)q.tile_x0[tile] + lane;
-        const uint64_t n = q.q_n[qi], L = q.q_L[qi];
-        const uint64_t m = n / x;
+        const uint64_t L = q.q_L[qi];
+        // keyed entries carry x and m; plain tiles are x0, x0+1, ... of query qi
+        const uint64_t x = x0 ? (uint64_t)x0 + lane : (uint64_t)q.key_x[g];
+        const uint64_t m = x0 ? q.q_n[qi] / x : q.x_m[g];
         const uint64_t k0 = L / x + 1;
         uint64_t K = (uint64_t)(q.beta * (double)isqrt64(m));
         if (K < k0 - 1)
@@ -308,11 +310,16 @@ __device__ inline uint32_t log_prime(uint32_t p)
     return (32u - (uint32_t)__clz((int)(p - 1u))) | 1u;
 }
 
-// Per block: residues of y1 modulo every sieving prime and square.
+// Per block: residues of y1 modulo every sieving prime and square; cleared
+// look-back states and segment ticket for the sieve.
 __global__ void k_block_setup(BlockArgs b_in)
 {
     const BlockArgs b = load_block(b_in);
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0)
+        *b.seg_ticket = 0;
+    if (i < b.nseg)
+        b.seg_state[i] = 0;
     if (i >= b.n_sieve)
         return;
     const uint64_t p = b.pres[i].x;
@@ -323,10 +330,50 @@ __global__ void k_block_setup(BlockArgs b_in)
 
 hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s)
 {
-    if (b.n_sieve == 0)
-        return hipSuccess;
-    hipLaunchKernelGGL(k_block_setup, dim3((b.n_sieve + 255) / 256), dim3(256), 0, s, b);
+    const uint32_t n = (b.n_sieve > b.nseg ? b.n_sieve : b.nseg) + 1;
+    hipLaunchKernelGGL(k_block_setup, dim3((n + 255) / 256), dim3(256), 0, s, b);
     return hipGetLastError();
+}
+
+// Look-back states of the fused scan.
+constexpr uint64_t SEG_AGG = 1ull << 62, SEG_INCL = 2ull << 62;
+constexpr uint64_t SEG_VAL = (1ull << 62) - 1;
+
+__device__ inline void seg_publish(uint64_t *st, uint32_t seg, uint64_t flag, int64_t v)
+{
+    __hip_atomic_store(st + seg, flag | ((uint64_t)v & SEG_VAL), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// M(y) just before segment seg (> 0), by wave 0 of its workgroup: the
+// lanes read the states of the 64 nearest unsummed predecessors and add
+// totals up to the first end-of-segment value.  Every predecessor holds an
+// earlier ticket, so it is running or done and its state arrives; segment
+// 0 always publishes its end value, which ends the walk.
+__device__ inline int64_t seg_lookback(const uint64_t *st, uint32_t seg)
+{
+    const uint32_t lane = lane_id();
+    int64_t acc = 0;
+    int64_t j = (int64_t)seg - 1;
+    for (;;) {
+        const int64_t idx = j - (int64_t)lane;
+        uint64_t v = 0;
+        if (idx >= 0)
+            v = __hip_atomic_load(st + idx, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t flag = v >> 62;
+        const uint64_t notready = __ballot(flag == 0);
+        const uint64_t incl = __ballot(flag == 2);
+        const uint32_t nr = notready ? (uint32_t)__builtin_ctzll(notready) : 64u;
+        const uint32_t fi = incl ? (uint32_t)__builtin_ctzll(incl) : 64u;
+        const uint32_t use = fi < nr ? fi + 1 : nr;
+        const int64_t val = (int64_t)(v << 2) >> 2;
+        acc += (int64_t)wave_sum_u64(lane < use ? (uint64_t)val : 0ull);
+        if (fi < nr)
+            return acc;
+        j -= use;
+        if (use == 0)
+            __builtin_amdgcn_s_sleep(2);
+    }
 }
 
 // One workgroup per segment of SEG consecutive y.  LDS holds one byte per y:
@@ -338,16 +385,22 @@ hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s)
 //   A >= floor(log2 y) (fully split) -> mu = (-1)^A
 //   otherwise (one prime > Psieve)   -> mu = -(-1)^A
 // (A's parity is the number of sieving primes dividing y, as every l_p is
-// odd.)  The result is stored as two 64-bit masks per 64 y.  Squares of
-// primes above SQ_LDS_P are cleared afterwards by k_square_fix.
+// odd.)  Segments are claimed in ticket order; each writes whole 32-byte
+// records per 64 y (two masks and M(y) before the word), the M(y) prefix
+// coming from a workgroup scan plus a look-back over earlier segments.
 __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
 {
     const BlockArgs b = load_block(b_in);
     __shared__ uint32_t lds[SEG / 4];
-    const uint32_t seg = blockIdx.x;
+    __shared__ int64_t wsum[SIEVE_THREADS / 64];
+    __shared__ int64_t bcast[2];  // ticket, M(y) before the segment
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    if (tid == 0)
+        bcast[0] = atomicAdd(b.seg_ticket, 1u);
+    __syncthreads();
+    const uint32_t seg = __builtin_amdgcn_readfirstlane((uint32_t)bcast[0]);
     if (seg >= b.nseg)
         return;
-    const uint32_t tid = threadIdx.x, lane = lane_id();
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     constexpr uint32_t NWAVES = SIEVE_THREADS / 64;
     const uint32_t segbase = seg * SEG;  // < 2^31
@@ -408,9 +461,37 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
                 atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
         }
     }
+    // squares p^2 > SQ_LDS_P^2 (> SEG): at most one multiple in the segment.
+    // f = offset of the block's first multiple; the segment's first is
+    // f - segbase mod p^2, with the quotient estimated in fp32 (t < 2^31,
+    // error < 1) and corrected once.
+    for (uint32_t i = b.n_sq_lds + tid; i < b.n_sq; i += SIEVE_THREADS) {
+        const uint64_t p = b.pres[i].x;
+        const uint64_t d = p * p;
+        const uint64_t r2 = b.res2[i];
+        const uint64_t f = r2 ? d - r2 : 0;
+        uint64_t o;
+        if (f >= segbase) {
+            o = f - segbase;
+        } else {
+            const uint32_t t = segbase - (uint32_t)f;
+            const uint64_t qt = (uint64_t)((float)t / (float)d);
+            int64_t rem = (int64_t)t - (int64_t)(qt * d);
+            if (rem < 0)
+                rem += (int64_t)d;
+            else if (rem >= (int64_t)d)
+                rem -= (int64_t)d;
+            o = rem ? d - (uint64_t)rem : 0;
+        }
+        if (o < SEG)
+            atomicOr(&lds[o >> 2], 0x80u << ((uint32_t)(o & 3u) << 3));
+    }
     __syncthreads();
 
     // classify: thread t owns words t and t + SIEVE_THREADS of the segment
+    uint64_t nzw[2], ngw[2];
+    int64_t cnt[2];
+#pragma unroll
     for (int h = 0; h < 2; ++h) {
         const uint32_t w = tid + (uint32_t)h * SIEVE_THREADS;
         const uint64_t ybase = s0 + (uint64_t)w * 64;
@@ -424,27 +505,61 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
             for (int g4 = 0; g4 < 4; ++g4) {
                 const uint32_t g = (uint32_t)(j * 4 + g4);
                 const uint64_t y = ybase + 4 * g;
-                uint32_t nzn, ngn;
-                if (y < 4) {
-                    nzn = 0xEu;  // mu(0..3) = 0, 1, -1, -1
-                    ngn = 0xCu;
-                } else {
-                    const uint32_t T = 63u - (uint32_t)__clzll((long long)y);  // floor(log2 y)
-                    const uint32_t x = vs[g4];
-                    const uint32_t F = ((x & 0x7f7f7f7fu) + (128u - T) * 0x01010101u) & 0x80808080u;
-                    const uint32_t par = (x & 0x01010101u) << 7;
-                    const uint32_t nzb = ~x & 0x80808080u;
-                    const uint32_t ngb = ~(F ^ par) & nzb;
-                    nzn = ((nzb >> 7) * 0x10204080u) >> 28;
-                    ngn = ((ngb >> 7) * 0x10204080u) >> 28;
-                }
+                // floor(log2 y) of the group's first y; the group's 4 y
+                // share it (y is a multiple of 4); y < 4 is patched below
+                const uint32_t T = 63u - (uint32_t)__clzll((long long)(y | 1));
+                const uint32_t x = vs[g4];
+                const uint32_t F = ((x & 0x7f7f7f7fu) + (128u - T) * 0x01010101u) & 0x80808080u;
+                const uint32_t par = (x & 0x01010101u) << 7;
+                const uint32_t nzb = ~x & 0x80808080u;
+                const uint32_t ngb = ~(F ^ par) & nzb;
+                const uint32_t nzn = ((nzb >> 7) * 0x10204080u) >> 28;
+                const uint32_t ngn = ((ngb >> 7) * 0x10204080u) >> 28;
                 nz |= (uint64_t)nzn << (4 * g);
                 ng |= (uint64_t)ngn << (4 * g);
             }
         }
-        const uint64_t gw = (uint64_t)seg * SEG_WORDS + w;
-        *reinterpret_cast<ulonglong2 *>(b.words + 4 * gw) = make_ulonglong2(nz, ng);
+        if (ybase == 0) {  // mu(0..3) = 0, 1, -1, -1
+            nz = (nz & ~0xFull) | 0xEull;
+            ng = (ng & ~0xFull) | 0xCull;
+        }
+        nzw[h] = nz;
+        ngw[h] = ng;
+        cnt[h] = (int64_t)__popcll(nz) - 2 * (int64_t)__popcll(ng);
     }
+
+    // fused M(y) prefix: within the segment by a workgroup scan, across
+    // segments by decoupled look-back (Section 4's running sum of mu)
+    int64_t tot0, tot1;
+    const int64_t ex0 = wg_exclusive_scan<SIEVE_THREADS>(cnt[0], wsum, tot0);
+    const int64_t ex1 = wg_exclusive_scan<SIEVE_THREADS>(cnt[1], wsum, tot1);
+    const int64_t T = tot0 + tot1;
+    if (tid < 64) {
+        int64_t before;
+        if (seg == 0) {
+            before = *b.carry;
+        } else {
+            if (tid == 0)
+                seg_publish(b.seg_state, seg, SEG_AGG, T);
+            before = seg_lookback(b.seg_state, seg);
+        }
+        if (tid == 0) {
+            seg_publish(b.seg_state, seg, SEG_INCL, before + T);
+            bcast[1] = before;
+            if (seg == b.nseg - 1)
+                *b.carry = before + T;
+        }
+    }
+    __syncthreads();
+    const int64_t P = bcast[1];
+    // whole 32-byte records {squarefree bits, mu = -1 bits, M before the word, 0}
+    const uint64_t gw0 = (uint64_t)seg * SEG_WORDS + tid;
+    ulonglong2 *r0 = reinterpret_cast<ulonglong2 *>(b.words + 4 * gw0);
+    r0[0] = make_ulonglong2(nzw[0], ngw[0]);
+    r0[1] = make_ulonglong2((uint64_t)(P + ex0), 0ull);
+    ulonglong2 *r1 = reinterpret_cast<ulonglong2 *>(b.words + 4 * (gw0 + SIEVE_THREADS));
+    r1[0] = make_ulonglong2(nzw[1], ngw[1]);
+    r1[1] = make_ulonglong2((uint64_t)(P + tot0 + ex1), 0ull);
 }
 
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s)
@@ -453,113 +568,7 @@ hipError_t launch_sieve(const BlockArgs &b, hipStream_t s)
     return hipGetLastError();
 }
 
-// Squares p^2 of primes p > SQ_LDS_P with p^2 <= y2: clear their multiples in
-// [y1, y2] from both masks (mu = 0).  One thread per prime; at most
-// B / 2^20 multiples each.
-__global__ void k_square_fix(BlockArgs b_in)
-{
-    const BlockArgs b = load_block(b_in);
-    const uint32_t i = b.n_sq_lds + blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= b.n_sq)
-        return;
-    const uint64_t p = b.pres[i].x;
-    const uint64_t p2 = p * p;
-    const uint64_t r = b.res2[i];
-    const uint64_t span = b.y2 - b.y1;
-    for (uint64_t o = r ? p2 - r : 0; o <= span; o += p2) {
-        const uint64_t w = o >> 6;
-        const unsigned long long keep = ~(1ull << (o & 63));
-        atomicAnd((unsigned long long *)&b.words[4 * w], keep);
-        atomicAnd((unsigned long long *)&b.words[4 * w + 1], keep);
-    }
-}
-
-hipError_t launch_square_fix(const BlockArgs &b, hipStream_t s)
-{
-    if (b.n_sq <= b.n_sq_lds)
-        return hipSuccess;
-    const uint32_t n = b.n_sq - b.n_sq_lds;
-    hipLaunchKernelGGL(k_square_fix, dim3((n + 255) / 256), dim3(256), 0, s, b);
-    return hipGetLastError();
-}
-
-// Per segment: exclusive prefix sums of mu over its mask words (mb, local to
-// the segment) and the segment's total.
-__global__ __launch_bounds__(SIEVE_THREADS) void k_scan_words(BlockArgs b_in)
-{
-    const BlockArgs b = load_block(b_in);
-    __shared__ int64_t wsum[SIEVE_THREADS / 64];
-    const uint32_t seg = blockIdx.x, tid = threadIdx.x;
-    if (seg >= b.nseg)
-        return;
-    const uint64_t gw0 = (uint64_t)seg * SEG_WORDS + tid;
-    const uint64_t gw1 = gw0 + SIEVE_THREADS;
-    const int64_t c0 = (int64_t)__popcll(b.words[4 * gw0]) - 2 * (int64_t)__popcll(b.words[4 * gw0 + 1]);
-    const int64_t c1 = (int64_t)__popcll(b.words[4 * gw1]) - 2 * (int64_t)__popcll(b.words[4 * gw1 + 1]);
-    int64_t tot0, tot1;
-    const int64_t ex0 = wg_exclusive_scan<SIEVE_THREADS>(c0, wsum, tot0);
-    const int64_t ex1 = wg_exclusive_scan<SIEVE_THREADS>(c1, wsum, tot1);
-    b.words[4 * gw0 + 2] = (uint64_t)ex0;
-    b.words[4 * gw1 + 2] = (uint64_t)(tot0 + ex1);
-    if (tid == 0)
-        b.seg_sum[seg] = (int32_t)(tot0 + tot1);
-}
-
-hipError_t launch_scan_words(const BlockArgs &b, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_scan_words, dim3(b.nseg), dim3(SIEVE_THREADS), 0, s, b);
-    return hipGetLastError();
-}
-
-// ====================================================================
-// a2: M(y) prefix scan across the segments of a block, carrying M(y1-1).
-// ====================================================================
 constexpr int SCAN_THREADS = 1024;
-
-__global__ __launch_bounds__(SCAN_THREADS) void k_scan_segments(BlockArgs b_in)
-{
-    const BlockArgs b = load_block(b_in);
-    __shared__ int64_t wsum[SCAN_THREADS / 64];
-    const uint32_t tid = threadIdx.x;
-    const uint32_t per = (b.nseg + SCAN_THREADS - 1) / SCAN_THREADS;
-    const uint32_t s_begin = tid * per;
-    const uint32_t s_end = (s_begin + per < b.nseg) ? s_begin + per : b.nseg;
-    int64_t local = 0;
-    for (uint32_t sgi = s_begin; sgi < s_end; ++sgi)
-        local += b.seg_sum[sgi];
-    const int64_t carry = *b.carry;
-    int64_t total;
-    const int64_t ex = wg_exclusive_scan<SCAN_THREADS>(local, wsum, total);
-    int64_t run = carry + ex;
-    for (uint32_t sgi = s_begin; sgi < s_end; ++sgi) {
-        b.seg_off[sgi] = run;
-        run += b.seg_sum[sgi];
-    }
-    __syncthreads();
-    if (tid == 0)
-        *b.carry = carry + total;
-}
-
-__global__ void k_fixup(BlockArgs b_in)
-{
-    const BlockArgs b = load_block(b_in);
-    const uint64_t w = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w < (uint64_t)b.nseg * SEG_WORDS)
-        b.words[4 * w + 2] += (uint64_t)b.seg_off[w / SEG_WORDS];
-}
-
-hipError_t launch_scan_segments(const BlockArgs &b, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_scan_segments, dim3(1), dim3(SCAN_THREADS), 0, s, b);
-    return hipGetLastError();
-}
-
-hipError_t launch_fixup(const BlockArgs &b, hipStream_t s)
-{
-    const uint64_t words = (uint64_t)b.nseg * SEG_WORDS;
-    hipLaunchKernelGGL(k_fixup, dim3((uint32_t)((words + 255) / 256)), dim3(256), 0, s, b);
-    return hipGetLastError();
-}
 
 // ====================================================================
 // a3: per-block contribution update.
@@ -896,8 +905,8 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
     // m as fp64; NaN on lanes past the tile's end, so their near-integer
     // test below never fires (they never write S)
     const double mfq = valid ? (double)m : __longlong_as_double(0x7ff8000000000000ll);
-    // lane 0 holds the tile's smallest x, hence its largest m
-    const uint64_t qbig = uniform_u64(m) >> 32;  // y > qbig => every quotient < 2^32
+    // y > qbig => every quotient of the tile is below 2^32
+    const uint64_t qbig = uniform_u64(wave_max_u64(m)) >> 32;
     const uint64_t ymin = uniform_u64(wave_min_u64(valid ? Y : ~0ull));
     const uint64_t y1e = b.y1 > 0 ? b.y1 : 1;
     const uint64_t tymax = uniform_u64(q.tile_ymax[tile]);
@@ -996,9 +1005,12 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
 
 // exact floor(m / k) for any k >= 1 from an fp64 estimate and integer
 // correction steps (one step suffices while the quotient is below 2^50)
-__device__ inline uint64_t div_fp_exact(uint64_t m, uint64_t k)
+// floor(m/k) from an fp64 estimate t of m/k: the remainder is corrected in
+// integers; the estimate is off by at most t * 2^-50 + 1, so the loops end
+// after a step or two for any quotient the sweep produces.
+__device__ inline uint64_t fix_quotient_any(uint64_t m, uint64_t k, double t)
 {
-    uint64_t qv = (uint64_t)((double)m / (double)k);
+    uint64_t qv = (uint64_t)t;
     int64_t r = (int64_t)(m - qv * k);
     while (r < 0) {
         qv -= 1;
@@ -1011,10 +1023,121 @@ __device__ inline uint64_t div_fp_exact(uint64_t m, uint64_t k)
     return qv;
 }
 
-// Explicit k part of one (tile, k-chunk) item: S[x] += M(floor(m_x / k)) for
-// k in the chunk and in x's range [klo, khi] of this block.
-__device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t tile, uint64_t c)
+// M(y1 + off) for K_UNROLL offsets at once: every record is requested
+// before any is used, so each lane keeps K_UNROLL gathers in flight (the
+// explicit k part is bound by gather latency, not by arithmetic).
+constexpr int K_UNROLL = 4;
+
+__device__ inline uint64_t M_sum_masked(const uint64_t *__restrict__ words,
+                                        const uint64_t (&off)[K_UNROLL],
+                                        const bool (&act)[K_UNROLL])
 {
+    ulonglong2 m2[K_UNROLL];
+    uint64_t mb[K_UNROLL];
+#pragma unroll
+    for (int u = 0; u < K_UNROLL; ++u) {
+        const uint64_t w = off[u] >> 6;
+        m2[u] = *reinterpret_cast<const ulonglong2 *>(words + 4 * w);
+        mb[u] = words[4 * w + 2];
+    }
+    uint64_t s = 0;
+#pragma unroll
+    for (int u = 0; u < K_UNROLL; ++u) {
+        const uint32_t bt = (uint32_t)(off[u] & 63);
+        const uint64_t lm = (2ull << bt) - 1ull;
+        const uint64_t v = mb[u] + (uint64_t)__popcll(m2[u].x & lm) -
+                           2ull * (uint64_t)__popcll(m2[u].y & lm);
+        s += act[u] ? v : 0ull;
+    }
+    return s;
+}
+
+// Explicit k part of one (tile, k-chunk) item with lanes as an 8 x 8 grid:
+// lane = 8 xi + kj takes x = 8 g + xi of x-group g and k = kk + kj, so one
+// gather instruction covers 8 neighbouring x and 8 neighbouring k, whose
+// quotients floor(m/k) lie closer together than 64 x at one k or 64 k at
+// one x (fewer cache lines per gather).  The reciprocals of the chunk's k
+// are computed once per sub-chunk into LDS; per-x sums are reduced over the
+// 8 k-lanes and leave with one 64-lane atomic per item.
+constexpr uint32_t K2D_SUB = 512;  // k per reciprocal sub-chunk (4 KB of LDS)
+
+__device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_t tile,
+                                 uint64_t c, double *rk)
+{
+    const uint32_t lane = lane_id(), xi = lane >> 3, kj = lane & 7u;
+    const uint32_t nx = __builtin_amdgcn_readfirstlane(q.tile_nx[tile]);
+    const uint64_t g0 = uniform_u64(q.tile_g0[tile]);
+    const uint64_t kb = uniform_u64(q.tile_klo[tile]) + c * q.kchunk;
+    const uint64_t tkhi = uniform_u64(q.tile_khi[tile]);
+    const uint64_t ke = (tkhi - kb) < (uint64_t)q.kchunk - 1 ? tkhi : kb + q.kchunk - 1;
+    uint64_t mine = 0;  // lane holds x = 8 kj + xi
+    for (uint64_t sb = kb; sb <= ke; sb += K2D_SUB) {
+        const uint64_t se = (ke - sb) < K2D_SUB - 1 ? ke : sb + K2D_SUB - 1;
+        const uint32_t ns = (uint32_t)(se - sb) + 1;
+        // the previous sub-chunk's readers are done with rk
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = lane; i < ns; i += 64)
+            rk[i] = 1.0 / (double)(sb + i);
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+        for (uint32_t g = 0; g < 8; ++g) {
+            const uint32_t xl = 8 * g + xi;
+            uint64_t m = 0, lo = 1, hi = 0;
+            if (xl < nx) {
+                m = q.x_m[g0 + xl];
+                lo = q.x_klo[g0 + xl];
+                hi = q.x_khi[g0 + xl];
+                lo = lo > sb ? lo : sb;
+                hi = hi < se ? hi : se;
+            }
+            const bool has = lo <= hi;
+            const uint64_t glo = uniform_u64(wave_min_u64(has ? lo : ~0ull));
+            const uint64_t ghi = uniform_u64(wave_max_u64(has ? hi : 0ull));
+            uint64_t acc = 0;
+            const double mf = (double)m;
+            for (uint64_t kk = glo; kk <= ghi; kk += 8 * K_UNROLL) {
+                uint64_t off[K_UNROLL];
+                bool act[K_UNROLL];
+#pragma unroll
+                for (int u = 0; u < K_UNROLL; ++u) {
+                    const uint64_t k = kk + 8 * u + kj;
+                    act[u] = k >= lo && k <= hi;
+                    const double qd = mf * rk[act[u] ? (uint32_t)(k - sb) : 0u];
+                    const double t = trunc(qd);
+                    // t is floor(m/k) when qd < 2^32 and not near an integer
+                    const bool fast = qd < 4294967296.0 && fabs(qd - t - 0.5) <= 0.5 - QEPS;
+                    uint64_t y = (uint64_t)(uint32_t)t;
+                    if (act[u] && !fast)
+                        y = fix_quotient_any(m, k, t);
+                    off[u] = act[u] ? y - b.y1 : 0ull;
+                }
+                acc += M_sum_masked(b.words, off, act);
+            }
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            acc += __shfl_xor(acc, 4, 64);
+            if (kj == g)
+                mine += acc;
+        }
+    }
+    const uint32_t xo = 8 * kj + xi;
+    if (xo < nx)
+        atomicAdd((unsigned long long *)&q.S[g0 + xo], (unsigned long long)mine);
+}
+
+// Explicit k part of one (tile, k-chunk) item: S[x] += M(floor(m_x / k)) for
+// k in the chunk and in x's range [klo, khi] of this block.  Mode 0 tiles
+// (k ranges of the tile's x overlap) use the 8 x 8 grid above; mode 1 tiles
+// (disjoint ranges) let each lane walk its own x's range in klchunk steps.
+__device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t tile, uint64_t c,
+                              double *rk)
+{
+    if (__builtin_amdgcn_readfirstlane(q.tile_mode[tile]) == 0) {
+        k_item_2d(q, b, tile, c, rk);
+        return;
+    }
     const uint32_t lane = lane_id();
     const uint32_t nx = q.tile_nx[tile];
     const uint64_t g = q.tile_g0[tile] + lane;
@@ -1023,79 +1146,46 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
     const uint64_t klo = valid ? q.x_klo[g] : 1;
     const uint64_t khi = valid ? q.x_khi[g] : 0;
     uint64_t acc = 0;
-    if (__builtin_amdgcn_readfirstlane(q.tile_mode[tile]) == 0) {
-        // uniform k across the wave
-        const double mf = (double)m;
-        const uint64_t qbig = uniform_u64(m) >> 32;  // k > qbig => quotients < 2^32
-        const uint64_t kb = uniform_u64(q.tile_klo[tile]) + c * q.kchunk;
-        const uint64_t tkhi = uniform_u64(q.tile_khi[tile]);
-        uint64_t ke = kb + q.kchunk - 1;
-        if (ke > tkhi)
-            ke = tkhi;
-        for (uint64_t kk = kb; kk <= ke; kk += 64) {
-            const uint32_t jmax = (ke - kk) < 63 ? (uint32_t)(ke - kk) : 63u;
-            if (kk > qbig) {
-                const double rl = 1.0 / (double)(kk + lane);
-                for (uint32_t j = 0; j <= jmax; ++j) {
-                    const uint64_t k = kk + j;
-                    const double qd = mf * readlane_f64(rl, j);
-                    if (k >= klo && k <= khi) {
-                        const double t = trunc(qd);
-                        // t < 2^32 unless the near-integer test fires
-                        uint64_t y = (uint32_t)t;
-                        if (fabs(qd - t - 0.5) > 0.5 - QEPS)
-                            y = fix_quotient(m, k, t);
-                        acc += (uint64_t)M_at(b.words, y - b.y1);
-                    }
-                }
-            } else {
-                uint64_t mul;
-                uint32_t sh1, sh2;
-                gm_magic((uint32_t)(kk + lane), mul, sh1, sh2);
-                for (uint32_t j = 0; j <= jmax; ++j) {
-                    const uint64_t k = kk + j;
-                    const uint64_t mg = readlane_u64(mul, j);
-                    const uint32_t s1 = __builtin_amdgcn_readlane(sh1, j);
-                    const uint32_t s2 = __builtin_amdgcn_readlane(sh2, j);
-                    if (k >= klo && k <= khi) {
-                        const uint64_t y = gm_div(m, mg, s1, s2);
-                        acc += (uint64_t)M_at(b.words, y - b.y1);
-                    }
-                }
-            }
+    const uint64_t ks = klo + c * q.klchunk;
+    uint64_t ke = ks + q.klchunk - 1;
+    if (ke > khi)
+        ke = khi;
+    const double mf = (double)m;
+    for (uint64_t k0 = ks; k0 <= ke && klo <= khi; k0 += K_UNROLL) {
+        uint64_t off[K_UNROLL];
+        bool act[K_UNROLL];
+#pragma unroll
+        for (int u = 0; u < K_UNROLL; ++u) {
+            const uint64_t k = k0 + u;
+            act[u] = k <= ke;
+            off[u] = 0;
+            if (act[u])
+                off[u] = fix_quotient_any(m, k, trunc(mf / (double)k)) - b.y1;
         }
-    } else {
-        // each lane walks its own sub-range
-        const uint64_t ks = klo + c * q.klchunk;
-        uint64_t ke = ks + q.klchunk - 1;
-        if (ke > khi)
-            ke = khi;
-        for (uint64_t k = ks; k <= ke && klo <= khi; ++k) {
-            const uint64_t y = div_fp_exact(m, k);
-            acc += (uint64_t)M_at(b.words, y - b.y1);
-        }
+        acc += M_sum_masked(b.words, off, act);
     }
     if (valid)
         atomicAdd((unsigned long long *)&q.S[g], (unsigned long long)acc);
 }
 
-// Persistent update kernel of one block: every wave takes work items from
-// a device counter until the block's items are exhausted.
+// Persistent update kernel of one block: wave w starts on item w and then
+// takes further items from a device counter until the block's items are
+// exhausted (a block with fewer items than waves costs no atomics beyond
+// one per item).
 __global__ __launch_bounds__(UPD_THREADS, 4) void k_update(QueryArgs q, BlockArgs b_in)
 {
-    __shared__ uint16_t ent_lds[UPD_THREADS / 64][RL_ENT_CAP];
+    // per wave: compacted run-length entries or explicit-k reciprocals
+    static_assert(RL_ENT_CAP * 2 >= K2D_SUB * 8, "LDS slice too small");
+    __shared__ double wave_lds[UPD_THREADS / 64][RL_ENT_CAP / 4];
     const BlockArgs b = load_block(b_in);
     const uint32_t lane = lane_id();
-    uint16_t *ent = ent_lds[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
+    double *wl = wave_lds[__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)];
+    uint16_t *ent = reinterpret_cast<uint16_t *>(wl);
     const uint64_t total = uniform_u64(q.tile_items[q.ntiles]);
+    const uint32_t nwaves = gridDim.x * (UPD_THREADS / 64);
+    uint64_t item = __builtin_amdgcn_readfirstlane(blockIdx.x * (UPD_THREADS / 64) +
+                                                   (threadIdx.x >> 6));
     for (;;) {
-        // One ticket per wave.  Every lane executes the atomic (lane 0 adds
-        // 1, the others 0) so the loop head holds no divergent branch, and
-        // readfirstlane turns the ticket into a scalar: the exit below is a
-        // uniform branch, and the compiler cannot split the wave across loop
-        // iterations around the cross-lane operations in the body.
-        const uint32_t it = atomicAdd(q.counter, lane == 0 ? 1u : 0u);
-        const uint64_t item = (uint32_t)__builtin_amdgcn_readfirstlane(it);
         if (item >= total)
             break;
         const uint32_t tile =
@@ -1105,7 +1195,14 @@ __global__ __launch_bounds__(UPD_THREADS, 4) void k_update(QueryArgs q, BlockArg
         if (local < nmu)
             mu_item(q, b, tile, local, ent);
         else
-            k_item(q, b, tile, local - nmu);
+            k_item(q, b, tile, local - nmu, wl);
+        // One ticket per wave.  Every lane executes the atomic (lane 0 adds
+        // 1, the others 0) so no divergent branch guards it, and readfirstlane
+        // turns the ticket into a scalar: the exit test is a uniform branch,
+        // and the compiler cannot split the wave across loop iterations
+        // around the cross-lane operations in the body.
+        const uint32_t it = atomicAdd(q.counter, lane == 0 ? 1u : 0u);
+        item = (uint64_t)nwaves + (uint32_t)__builtin_amdgcn_readfirstlane(it);
     }
 }
 
@@ -1124,10 +1221,104 @@ hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, 
 // ====================================================================
 constexpr int FIN_THREADS = 1024;
 
+// Entry of (x, m) in the keyed group starting at entry g0 with key_off base
+// kb (x <= L, and (x, m) is one of the group's pairs): binary search among
+// the sorted m of x's entries.
+__device__ inline uint64_t key_find(const QueryArgs &q, uint64_t g0, uint64_t kb, uint64_t x,
+                                    uint64_t m)
+{
+    uint64_t lo = g0 + q.key_off[kb + x - 1];
+    uint64_t hi = g0 + q.key_off[kb + x];
+    while (hi - lo > 1) {
+        const uint64_t mid = lo + (hi - lo) / 2;
+        if (q.x_m[mid] <= m)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return lo;
+}
+
+// Finalize of a keyed group: the same recursion over entries, with A[kx]
+// taken from the entry (kx, floor(m/k)), since floor(floor(n/x)/k) =
+// floor(n/(kx)).  Levels of x as in k_finalize; a level's entries are
+// independent.
+__device__ void finalize_keyed(const QueryArgs &q, uint32_t qi, uint64_t *red)
+{
+    const uint64_t L = q.q_L[qi];
+    const uint64_t g0 = q.q_g0[qi];
+    const uint64_t kb = q.q_koff[qi];
+    uint64_t *A = reinterpret_cast<uint64_t *>(q.A);
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (uint64_t hi = L, lo = L / 2; hi >= 1; hi = lo, lo = lo / 2) {
+        const uint64_t e0 = g0 + q.key_off[kb + lo], e1 = g0 + q.key_off[kb + hi];
+        const uint64_t ne = e1 - e0;
+        if (ne >= FIN_THREADS) {
+            for (uint64_t e = e0 + tid; e < e1; e += FIN_THREADS) {
+                const uint64_t x = q.key_x[e], m = q.x_m[e];
+                uint64_t s = 1 - q.S[e];
+                const uint64_t j = L / x;
+                for (uint64_t k = 2; k <= j; ++k)
+                    s -= A[key_find(q, g0, kb, k * x, m / k)];
+                A[e] = s;
+            }
+        } else if (ne > 4) {
+            uint32_t gsz = 1;
+            while (gsz < 64 && (uint64_t)gsz * 2 * ne <= FIN_THREADS)
+                gsz *= 2;
+            const uint32_t ngroups = FIN_THREADS / gsz;
+            const uint32_t grp = tid / gsz, sub = tid % gsz;
+            for (uint64_t base = 0; base < ne; base += ngroups) {  // same trip count for all
+                const uint64_t ei = base + grp;
+                const bool active = ei < ne;
+                const uint64_t e = e0 + ei;
+                uint64_t s = 0;
+                uint64_t x = 1, m = 0;
+                if (active) {
+                    x = q.key_x[e];
+                    m = q.x_m[e];
+                    const uint64_t j = L / x;
+                    for (uint64_t k = 2 + sub; k <= j; k += gsz)
+                        s += A[key_find(q, g0, kb, k * x, m / k)];
+                }
+                for (uint32_t o = gsz / 2; o >= 1; o >>= 1)
+                    s += __shfl_xor(s, (int)o, 64);
+                if (active && sub == 0)
+                    A[e] = 1 - q.S[e] - s;
+            }
+        } else {
+            for (uint64_t e = e0; e < e1; ++e) {
+                const uint64_t x = q.key_x[e], m = q.x_m[e];
+                const uint64_t j = L / x;
+                uint64_t s = 0;
+                for (uint64_t k = 2 + tid; k <= j; k += FIN_THREADS)
+                    s += A[key_find(q, g0, kb, k * x, m / k)];
+                s = wave_sum_u64(s);
+                if (lane == 0)
+                    red[wave] = s;
+                __syncthreads();
+                if (tid == 0) {
+                    uint64_t t = 0;
+                    for (int w = 0; w < FIN_THREADS / 64; ++w)
+                        t += red[w];
+                    A[e] = 1 - q.S[e] - t;
+                }
+                __syncthreads();
+            }
+        }
+        __syncthreads();
+    }
+}
+
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(QueryArgs q, const uint32_t *qlist)
 {
     __shared__ uint64_t red[FIN_THREADS / 64];
     const uint32_t qi = qlist ? qlist[blockIdx.x] : blockIdx.x;
+    if (q.q_koff[qi] != ~0ull) {
+        finalize_keyed(q, qi, red);
+        return;
+    }
     const uint64_t L = q.q_L[qi];
     const uint64_t g0 = q.q_g0[qi];
     const uint64_t *S = q.S + g0;
@@ -1202,8 +1393,28 @@ hipError_t launch_finalize(const QueryArgs &q, const uint32_t *qlist, uint32_t c
 __global__ void k_collect(QueryArgs q, int64_t *out)
 {
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < q.nq)
-        out[i] = q.A[q.q_g0[i]];
+    if (i >= q.nq)
+        return;
+    const uint64_t kb = q.q_koff[i];
+    out[i] = kb == ~0ull ? q.A[q.q_g0[i]] : q.A[key_find(q, q.q_g0[i], kb, 1, q.q_n[i])];
+}
+
+__global__ void k_keyed_byproducts(QueryArgs q, uint32_t qi, uint64_t count, int64_t *out)
+{
+    const uint64_t c = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x + 1;
+    if (c > count)
+        return;
+    out[c - 1] = q.A[key_find(q, q.q_g0[qi], q.q_koff[qi], c, q.q_n[qi] / c)];
+}
+
+hipError_t launch_keyed_byproducts(const QueryArgs &q, uint32_t qi, uint64_t count, int64_t *out,
+                                   hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_keyed_byproducts, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s,
+                       q, qi, count, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_collect(const QueryArgs &q, int64_t *out, hipStream_t s)

@@ -10,8 +10,8 @@
 //     blocks does not matter; within a pass the sieve carry runs in
 //     ascending y), and is finalized and returned on its own.
 // Per block the kernel sequence is (Section 3):
-//   residues -> sieve -> square fix -> word prefix -> segment prefix ->
-//   fixup -> update prep -> item prefix -> persistent update
+//   residues -> sieve with fused M(y) prefix -> update prep -> item prefix
+//   -> persistent update
 // with no host synchronisation inside a sweep.
 #include "mertens.h"
 #include "mertens_internal.h"
@@ -153,12 +153,12 @@ struct Tuning {
 struct SieveState {
     uint64_t psieve = 0;
     std::vector<uint32_t> h_primes;  // primes >= 5 up to psieve
-    DevBuf pres, res2, pattern, words, seg_sum, seg_off, carry, bp_cur, bp_table, bp_index;
+    DevBuf pres, res2, pattern, words, seg_state, carry, bp_cur, bp_table, bp_index;
     bool have_pattern = false;
 
     void release()
     {
-        DevBuf *bufs[] = {&pres, &res2, &pattern, &words, &seg_sum, &seg_off, &carry,
+        DevBuf *bufs[] = {&pres, &res2, &pattern, &words, &seg_state, &carry,
                           &bp_cur, &bp_table, &bp_index};
         for (DevBuf *b : bufs)
             b->release();
@@ -222,9 +222,8 @@ struct SieveState {
     int ensure_blocks(uint64_t B)
     {
         RCCHK(ensure(words, B / 64 * 32));
-        RCCHK(ensure(seg_sum, B / SEG * 4));
-        RCCHK(ensure(seg_off, B / SEG * 8));
-        RCCHK(ensure(carry, 64));
+        RCCHK(ensure(seg_state, B / SEG * 8));
+        RCCHK(ensure(carry, 64));  // M(y1 - 1) at byte 0, segment ticket at byte 8
         RCCHK(ensure(bp_cur, sizeof(BlockParams)));
         RCCHK(ensure(bp_index, 64));
         return 0;
@@ -253,8 +252,8 @@ struct SieveState {
         b.res2 = res2.as<uint64_t>();
         b.pat32 = pattern.as<uint32_t>();
         b.words = words.as<uint64_t>();
-        b.seg_sum = seg_sum.as<int32_t>();
-        b.seg_off = seg_off.as<int64_t>();
+        b.seg_state = seg_state.as<uint64_t>();
+        b.seg_ticket = reinterpret_cast<uint32_t *>(carry.as<uint8_t>() + 8);
         b.carry = carry.as<int64_t>();
         return b;
     }
@@ -282,9 +281,10 @@ struct SieveState {
         return b;
     }
 
-    // block parameters, residues, then the sieve (an event may be recorded
-    // before it so the sieve kernels are timed alone), then the large-square
-    // fix.  set_params = false when a graph node loads the parameters.
+    // block parameters, residues and cleared scan state, then the sieve with
+    // its fused M(y) prefix (an event may be recorded before it so the sieve
+    // is timed alone).  set_params = false when a graph node loads the
+    // parameters.
     int sieve(const BlockArgs &b, hipStream_t s, hipEvent_t between, bool set_params = true) const
     {
         if (set_params)
@@ -293,15 +293,6 @@ struct SieveState {
         if (between)
             HIPCHK(hipEventRecord(between, s));
         HIPCHK(launch_sieve(b, s));
-        HIPCHK(launch_square_fix(b, s));
-        return 0;
-    }
-
-    int scan(const BlockArgs &b, hipStream_t s) const
-    {
-        HIPCHK(launch_scan_words(b, s));
-        HIPCHK(launch_scan_segments(b, s));
-        HIPCHK(launch_fixup(b, s));
         return 0;
     }
 
@@ -316,36 +307,75 @@ struct SieveState {
 // One set of queries sharing a sweep: per-query plan and device state.
 // ---------------------------------------------------------------------------
 struct Batch {
-    std::vector<uint64_t> n, L, g0, ymax;
-    uint64_t X = 0, ymax_all = 0;
+    std::vector<uint64_t> n, L, g0, ymax, koff;
+    std::vector<uint32_t> fin_list;  // plain queries and one member per keyed group
+    uint64_t X = 0, ymax_all = 0, keyed_entries = 0;
     uint32_t ntiles = 0;
-    DevBuf q_n, q_L, q_g0, x_m, x_Y, x_K, x_k0, S, A, x_klo, x_khi;
+    DevBuf q_n, q_L, q_g0, q_koff, x_m, x_Y, x_K, x_k0, S, A, x_klo, x_khi, key_x, key_off;
     DevBuf tile_q, tile_x0, tile_nx, tile_g0, tile_ymax, tile_klo, tile_khi, tile_mode, tile_nmu,
-        tile_items, counter, pair_stats, out_dev, qlist;
+        tile_items, counter, pair_stats, out_dev, qlist, byp;
     QueryArgs args{};
 
     void release()
     {
-        DevBuf *bufs[] = {&q_n, &q_L, &q_g0, &x_m, &x_Y, &x_K, &x_k0, &S, &A, &x_klo, &x_khi,
-                          &tile_q, &tile_x0, &tile_nx, &tile_g0, &tile_ymax, &tile_klo,
-                          &tile_khi, &tile_mode, &tile_nmu, &tile_items, &counter, &pair_stats,
-                          &out_dev, &qlist};
+        DevBuf *bufs[] = {&q_n, &q_L, &q_g0, &q_koff, &x_m, &x_Y, &x_K, &x_k0, &S, &A, &x_klo,
+                          &x_khi, &key_x, &key_off, &tile_q, &tile_x0, &tile_nx, &tile_g0,
+                          &tile_ymax, &tile_klo, &tile_khi, &tile_mode, &tile_nmu, &tile_items,
+                          &counter, &pair_stats, &out_dev, &qlist, &byp};
         for (DevBuf *b : bufs)
             b->release();
     }
 
+    // The distinct pairs (x, floor(v/x)) over the ascending values v[] for
+    // x = 1..Lg, sorted by x then m, with the first entry of each x in off[]
+    // (off[Lg] = number of entries).  Per x, the next value with a larger
+    // quotient is found by binary search: work ~ entries * log(#values).
+    static int make_keys(const std::vector<uint64_t> &v, uint64_t Lg, std::vector<uint32_t> &kx,
+                         std::vector<uint64_t> &km, std::vector<uint32_t> &off)
+    {
+        kx.clear();
+        km.clear();
+        off.assign(Lg + 1, 0);
+        for (uint64_t x = 1; x <= Lg; ++x) {
+            if (km.size() >= 0xFFFFFFFFull) {
+                set_error_text("too many distinct (x, n/x) entries in one group");
+                return MERTENS_EINVAL;
+            }
+            off[x - 1] = (uint32_t)km.size();
+            size_t i = 0;
+            while (i < v.size()) {
+                const uint64_t m = v[i] / x;
+                kx.push_back((uint32_t)x);
+                km.push_back(m);
+                if (m + 1 > UINT64_MAX / x)
+                    break;  // no value reaches (m+1) x
+                const uint64_t next = (m + 1) * x;
+                i = (size_t)(std::lower_bound(v.begin() + (ptrdiff_t)i + 1, v.end(), next) -
+                             v.begin());
+            }
+        }
+        off[Lg] = (uint32_t)km.size();
+        return 0;
+    }
+
     // Plan the queries ns[i] with split us[i] (Section 2: L = max(1, n/u)
-    // array entries; the sieve covers [1, n/(L+1)]).
+    // array entries; the sieve covers [1, n/(L+1)]).  With `group`, queries
+    // of equal L share one keyed set of entries (their contributions depend
+    // on x and floor(n/x) only), so a dense window of n costs its distinct
+    // quotients rather than one array per n.
     int plan(const std::vector<uint64_t> &ns, const std::vector<uint64_t> &us, const Tuning &t,
-             hipStream_t s)
+             hipStream_t s, bool group = true)
     {
         const size_t nq = ns.size();
         n = ns;
         L.assign(nq, 0);
         g0.assign(nq, 0);
         ymax.assign(nq, 0);
+        koff.assign(nq, ~0ull);
+        fin_list.clear();
         X = 0;
         ymax_all = 0;
+        keyed_entries = 0;
         for (size_t i = 0; i < nq; ++i) {
             uint64_t Li = ns[i] / us[i];
             if (Li < 1)
@@ -355,20 +385,70 @@ struct Batch {
                 return MERTENS_EINVAL;
             }
             L[i] = Li;
-            g0[i] = X;
-            X += Li;
             ymax[i] = ns[i] / (Li + 1);
             ymax_all = std::max(ymax_all, ymax[i]);
         }
+        // groups of equal L (ascending n inside a group)
+        std::vector<size_t> order(nq);
+        for (size_t i = 0; i < nq; ++i)
+            order[i] = i;
+        if (group)
+            std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+                return L[a] != L[b] ? L[a] < L[b] : ns[a] < ns[b];
+            });
         std::vector<uint32_t> t_q, t_x0, t_nx;
         std::vector<uint64_t> t_g0;
-        for (size_t i = 0; i < nq; ++i)
-            for (uint64_t x0 = 1; x0 <= L[i]; x0 += TILE) {
-                t_q.push_back((uint32_t)i);
-                t_x0.push_back((uint32_t)x0);
-                t_nx.push_back((uint32_t)std::min<uint64_t>(TILE, L[i] - x0 + 1));
-                t_g0.push_back(g0[i] + x0 - 1);
+        struct KeyedGroup {
+            uint64_t g0;
+            std::vector<uint32_t> kx;
+            std::vector<uint64_t> km;
+        };
+        std::vector<KeyedGroup> kgroups;
+        std::vector<uint32_t> h_key_off;
+        for (size_t a = 0; a < nq;) {
+            size_t b = a + 1;
+            while (group && b < nq && L[order[b]] == L[order[a]])
+                ++b;
+            const uint64_t Lg = L[order[a]];
+            if (b - a == 1) {
+                const size_t i = order[a];
+                g0[i] = X;
+                fin_list.push_back((uint32_t)i);
+                for (uint64_t x0 = 1; x0 <= Lg; x0 += TILE) {
+                    t_q.push_back((uint32_t)i);
+                    t_x0.push_back((uint32_t)x0);
+                    t_nx.push_back((uint32_t)std::min<uint64_t>(TILE, Lg - x0 + 1));
+                    t_g0.push_back(X + x0 - 1);
+                }
+                X += Lg;
+            } else {
+                std::vector<uint64_t> v;
+                for (size_t j = a; j < b; ++j)
+                    v.push_back(ns[order[j]]);
+                KeyedGroup kg;
+                kg.g0 = X;
+                std::vector<uint32_t> off;
+                RCCHK(make_keys(v, Lg, kg.kx, kg.km, off));
+                const uint64_t base = h_key_off.size();
+                h_key_off.insert(h_key_off.end(), off.begin(), off.end());
+                for (size_t j = a; j < b; ++j) {
+                    g0[order[j]] = X;
+                    koff[order[j]] = base;
+                }
+                fin_list.push_back((uint32_t)order[a]);
+                const uint64_t E = kg.km.size();
+                for (uint64_t e = 0; e < E; e += TILE) {
+                    t_q.push_back((uint32_t)order[a]);
+                    t_x0.push_back(0u);
+                    t_nx.push_back((uint32_t)std::min<uint64_t>(TILE, E - e));
+                    t_g0.push_back(X + e);
+                }
+                X += E;
+                keyed_entries += E;
+                kgroups.push_back(std::move(kg));
             }
+            a = b;
+        }
         const size_t nt = t_q.size();
         if (nt >= (1ull << 31)) {
             set_error_text("too many tiles");
@@ -378,9 +458,12 @@ struct Batch {
         RCCHK(ensure(q_n, nq * 8));
         RCCHK(ensure(q_L, nq * 8));
         RCCHK(ensure(q_g0, nq * 8));
+        RCCHK(ensure(q_koff, nq * 8));
         DevBuf *xb[] = {&x_m, &x_Y, &x_K, &x_k0, &S, &A, &x_klo, &x_khi};
         for (DevBuf *b : xb)
             RCCHK(ensure(*b, X * 8));
+        RCCHK(ensure(key_x, std::max<uint64_t>(X, 1) * 4));
+        RCCHK(ensure(key_off, std::max<size_t>(h_key_off.size(), 1) * 4));
         RCCHK(ensure(tile_q, nt * 4));
         RCCHK(ensure(tile_x0, nt * 4));
         RCCHK(ensure(tile_nx, nt * 4));
@@ -398,6 +481,16 @@ struct Batch {
         HIPCHK(hipMemcpyAsync(q_n.p, n.data(), nq * 8, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(q_L.p, L.data(), nq * 8, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(q_g0.p, g0.data(), nq * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(q_koff.p, koff.data(), nq * 8, hipMemcpyHostToDevice, s));
+        if (!h_key_off.empty())
+            HIPCHK(hipMemcpyAsync(key_off.p, h_key_off.data(), h_key_off.size() * 4,
+                                  hipMemcpyHostToDevice, s));
+        for (const KeyedGroup &kg : kgroups) {
+            HIPCHK(hipMemcpyAsync(key_x.as<uint32_t>() + kg.g0, kg.kx.data(), kg.kx.size() * 4,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(x_m.as<uint64_t>() + kg.g0, kg.km.data(), kg.km.size() * 8,
+                                  hipMemcpyHostToDevice, s));
+        }
         HIPCHK(hipMemcpyAsync(tile_q.p, t_q.data(), nt * 4, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(tile_x0.p, t_x0.data(), nt * 4, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(tile_nx.p, t_nx.data(), nt * 4, hipMemcpyHostToDevice, s));
@@ -410,6 +503,9 @@ struct Batch {
         q.q_n = q_n.as<uint64_t>();
         q.q_L = q_L.as<uint64_t>();
         q.q_g0 = q_g0.as<uint64_t>();
+        q.q_koff = q_koff.as<uint64_t>();
+        q.key_x = key_x.as<uint32_t>();
+        q.key_off = key_off.as<uint32_t>();
         q.x_m = x_m.as<uint64_t>();
         q.x_Y = x_Y.as<uint64_t>();
         q.x_K = x_K.as<uint64_t>();
@@ -456,7 +552,10 @@ struct Batch {
     int finalize(const std::vector<uint32_t> &which, hipStream_t s)
     {
         if (which.empty()) {
-            HIPCHK(launch_finalize(args, nullptr, args.nq, s));
+            HIPCHK(hipMemcpyAsync(qlist.p, fin_list.data(), fin_list.size() * 4,
+                                  hipMemcpyHostToDevice, s));
+            HIPCHK(launch_finalize(args, qlist.as<uint32_t>(), (uint32_t)fin_list.size(), s));
+            HIPCHK(hipStreamSynchronize(s));  // fin_list may change with the next plan
         } else {
             HIPCHK(hipMemcpyAsync(qlist.p, which.data(), which.size() * 4, hipMemcpyHostToDevice,
                                   s));
@@ -531,6 +630,7 @@ struct Ctx {
     Batch batch;
     // last query (for byproducts): per caller index, L and first global index
     std::vector<uint64_t> last_L, last_g0;
+    std::vector<int64_t> last_j;  // index in the batch, -1 for n = 0
     bool last_valid = false;
     double stats[16] = {0};
     std::vector<hipEvent_t> events;
@@ -555,6 +655,7 @@ void free_all()
     g.stream = nullptr;
     g.last_L.clear();
     g.last_g0.clear();
+    g.last_j.clear();
     g.last_valid = false;
     g.ready = false;
 }
@@ -633,8 +734,6 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
         if (!rc)
             rc = g.ss.sieve(bm, s, nullptr, false);
         if (!rc)
-            rc = g.ss.scan(bm, s);
-        if (!rc)
             rc = bt.update_block(bm, grid, s, nullptr);
         const hipError_t ec = hipStreamEndCapture(s, &graph);
         if (rc)
@@ -655,8 +754,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
         marks.push_back(ev);
         RCCHK(g.ss.sieve(b, s, g.events[ev]));
         HIPCHK(hipEventRecord(g.events[ev + 1], s));
-        RCCHK(g.ss.scan(b, s));
-        HIPCHK(hipEventRecord(g.events[ev + 2], s));
+        HIPCHK(hipEventRecord(g.events[ev + 2], s));  // (no separate scan pass)
         RCCHK(bt.update_block(b, grid, s, g.events[ev + 3]));
         HIPCHK(hipEventRecord(g.events[ev + 4], s));
         ev += 5;
@@ -727,7 +825,8 @@ int serve_step(std::vector<uint64_t> &admit)
         }
         for (uint64_t x : ns)
             us.push_back(g.u_req ? g.u_req : auto_u((long double)x, g.tune.u_scale));
-        RCCHK(sb->b.plan(ns, us, g.tune, s));
+        // no keyed groups here: requests complete and finalize one by one
+        RCCHK(sb->b.plan(ns, us, g.tune, s, false));
         sb->tickets = admit;
         sb->open = admit.size();
         sb->x_entries = sb->b.X;
@@ -768,7 +867,6 @@ int serve_step(std::vector<uint64_t> &admit)
     const uint64_t y2 = y1 + B - 1;
     const BlockArgs b = v.ss.make_block(y1, y2);
     RCCHK(v.ss.sieve(b, s, nullptr));
-    RCCHK(v.ss.scan(b, s));
     const uint32_t grid = update_grid(g.ncu, g.tune);
     for (auto &sb : v.batches)
         if (sb->open)
@@ -975,12 +1073,14 @@ int mertens_query(const uint64_t *n, size_t count, int64_t *out)
     }
     g.last_L.assign(count, 0);
     g.last_g0.assign(count, 0);
+    g.last_j.assign(count, -1);
     for (size_t i = 0; i < count; ++i)
         out[i] = 0;
     for (size_t j = 0; j < where.size(); ++j) {
         out[where[j]] = res[j];
         g.last_L[where[j]] = g.batch.L[j];
         g.last_g0[where[j]] = g.batch.g0[j];
+        g.last_j[where[j]] = (int64_t)j;
     }
     g.last_valid = true;
     return 0;
@@ -998,11 +1098,20 @@ int mertens_byproducts(size_t i, int64_t *buf, size_t cap, size_t *len)
     if (len)
         *len = (size_t)L;
     const size_t k = (size_t)std::min<uint64_t>(L, cap);
-    if (k > 0) {
+    if (k == 0)
+        return 0;
+    const int64_t j = g.last_j[i];
+    if (j >= 0 && g.batch.koff[(size_t)j] != ~0ull) {
+        // member of a keyed group: gather its entries (c, floor(n/c))
+        RCCHK(ensure(g.batch.byp, k * 8));
+        HIPCHK(launch_keyed_byproducts(g.batch.args, (uint32_t)j, k, g.batch.byp.as<int64_t>(),
+                                       g.stream));
+        HIPCHK(hipMemcpyAsync(buf, g.batch.byp.p, k * 8, hipMemcpyDeviceToHost, g.stream));
+    } else {
         HIPCHK(hipMemcpyAsync(buf, g.batch.A.as<int64_t>() + g.last_g0[i], k * 8,
                               hipMemcpyDeviceToHost, g.stream));
-        HIPCHK(hipStreamSynchronize(g.stream));
     }
+    HIPCHK(hipStreamSynchronize(g.stream));
     return 0;
 }
 
@@ -1240,7 +1349,7 @@ int mertens_debug_mu(uint64_t y1, size_t count, int8_t *mu, int64_t *mert)
     for (uint64_t y = start; e == hipSuccess && y <= yend; y += B) {
         const uint64_t y2 = std::min(y + B - 1, yend);
         const BlockArgs b = g.ss.make_block(y, y2);
-        if (g.ss.sieve(b, g.stream, nullptr) != 0 || g.ss.scan(b, g.stream) != 0) {
+        if (g.ss.sieve(b, g.stream, nullptr) != 0) {
             e = hipErrorUnknown;
             break;
         }

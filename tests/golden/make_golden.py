@@ -46,6 +46,11 @@ def main() -> None:
     out["batch48"] = {"seed": 1, "n": [int(v) for v in nb],
                       "M": [o2.query(int(v))[0] for v in nb]}
 
+    # a dense window: n_i = n0 + 997 i, i < 8, n0 uniform in [1e12, 2e12] (seed 2)
+    nw = inputs.dense_window(seed=2, count=8, lo=10**12, hi=2 * 10**12)
+    out["window1e12"] = {"seed": 2, "n": [int(v) for v in nw],
+                         "M": [o2.query(int(v))[0] for v in nw]}
+
     path = os.path.join(HERE, "golden.json")
     with open(path, "w") as f:
         json.dump(out, f)

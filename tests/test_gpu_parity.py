@@ -187,3 +187,47 @@ def test_graph_replays_match_eager(mt):
         assert list(mt.query(GOLDEN["batch48"]["n"][:8])) == GOLDEN["batch48"]["M"][:8]
     _reinit(mt, u=5 * 10**10, block=1 << 30, graph=1)
     assert int(mt.query([10**16])[0]) == inputs.TABLE1[10**16]
+
+
+# ------------------------------------------------------------------ dense windows (keyed groups)
+
+def test_window_keyed_small_vs_oracle(mt):
+    # 64 n 997 apart share L = n/u: one keyed group of distinct (x, n/x)
+    _reinit(mt, u=10**7, block=1 << 24)
+    ns = inputs.dense_window(seed=3, count=64, lo=9 * 10**8, hi=10**9 - 64 * 997)
+    got = mt.query(ns)
+    assert np.array_equal(got, oracle.mertens_many(ns))
+    # every byproduct M(floor(n_i/c)) of a few members
+    for i in (0, 17, 63):
+        n = int(ns[i])
+        byp = mt.byproducts(i)
+        assert byp.size == n // 10**7
+        args = np.array([n // c for c in range(1, byp.size + 1)], dtype=np.uint64)
+        order = np.argsort(args)
+        ref = np.empty(args.size, dtype=np.int64)
+        ref[order] = oracle.mertens_many(args[order])
+        assert np.array_equal(byp, ref)
+
+
+def test_window1e12_golden(mt):
+    _reinit(mt)
+    g = GOLDEN["window1e12"]
+    ns = inputs.dense_window(seed=g["seed"], count=8, lo=10**12, hi=2 * 10**12)
+    assert [int(v) for v in ns] == g["n"]
+    assert list(mt.query(g["n"])) == g["M"]
+
+
+def test_window_keyed_matches_plain(mt):
+    # a window near 1e15 with a fixed u: the keyed group against each n alone
+    # (one query has its own plain array), results and byproducts
+    _reinit(mt, u=10**10, block=1 << 28)
+    ns = [10**15 + 31 + 997 * i for i in range(16)] + [10**15 + 31]  # with a duplicate
+    got = [int(v) for v in mt.query(ns)]
+    byp = [mt.byproducts(i) for i in (0, 5, 15, 16)]
+    alone = []
+    for i, n in enumerate(ns):
+        alone.append(int(mt.query([n])[0]))
+        if i in (0, 5, 15):
+            assert np.array_equal(mt.byproducts(0), byp[(0, 5, 15).index(i)])
+    assert got == alone
+    assert np.array_equal(byp[3], byp[0])
