@@ -131,11 +131,20 @@ int mertens_set_stream(void *hip_stream);
  *   "u_scale"     automatic u = u_scale * (sum of the batch's n)^(2/3); default 1
  *   "beta"        split of the per-x sum between the run-length part over
  *                 y <= Y and the explicit k part (K = floor(beta*sqrt(m))),
- *                 in (0, 1]; default 0.2
+ *                 in (0, 1]; default 0.25
  *   "ychunk"      y per work item of the run-length part, multiple of 64
- *                 in [64, 2^20] (default 4096)
- *   "kchunk"      k per work item of the explicit k part
- *   "waves_per_cu" persistent update grid size per compute unit
+ *                 in [64, 2^20] (default 16384)
+ *   "kchunk"      k per work item of the explicit k part (default 1024)
+ *   "klchunk"     k per lane and work item where a tile's x have disjoint
+ *                 k ranges (default 256)
+ *   "waves_per_cu" persistent update grid size per compute unit (default 16)
+ *   "graph"       1: replay one captured hipGraph of the per-block kernel
+ *                 sequence; 0: direct launches (default)
+ *   "sieve_ahead" direct launches: most blocks sieved ahead of the update on
+ *                 a second stream, each holding B/2 bytes of records
+ *                 (default 4; 1 = strictly in turn)
+ *   "rl_fast"     1 (default): run-length quotients with m < 2^48 take the
+ *                 test-free rounded-up fp64 floor; 0: always the tested path
  *   "serve_capacity"  most requests in flight for mertens_submit (4096)
  *   "serve_x_budget"  most x entries of admitted requests (2^26 = 4 GiB)
  * Returns 0 or MERTENS_EINVAL (unknown key, value out of range, or a

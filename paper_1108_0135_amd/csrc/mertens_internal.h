@@ -92,6 +92,7 @@ struct QueryArgs {
     // tuning
     double beta;
     uint32_t ychunk, kchunk, klchunk;
+    uint32_t rl_fast;  // 1: check-free fp64 floors where every m < 2^48
 };
 
 // ---------------------------------------------------------------- launchers

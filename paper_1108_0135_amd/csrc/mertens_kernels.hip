@@ -602,10 +602,12 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockA
             klo = lo;
             khi = hi;
         }
-        q.x_klo[g] = klo;
-        q.x_khi[g] = khi;
         if (Y >= y1e && Y <= b.y2)
             q.S[g] -= K * (uint64_t)M_at(b.words, Y - b.y1);
+    }
+    if (lane < nx) {
+        q.x_klo[g] = klo;
+        q.x_khi[g] = khi;
     }
     const bool has = klo <= khi;
     const uint64_t kpairs = wave_sum_u64(has ? khi - klo + 1 : 0ull);
@@ -722,33 +724,52 @@ constexpr int RL_XS = 16;
 constexpr uint32_t RL_ENT_SPAN = 4096;  // y per compacted sub-chunk
 constexpr uint32_t RL_ENT_CAP = 3072;   // 1024 of any 4096 consecutive y are multiples of 4
 
+// Below this m the rounded-up reciprocal gives exact floors with no test.
+constexpr double RL_M_EXACT = 281474976710656.0;  // 2^48
+
 // One pass of RL_XS x (m as fp64 in mf, NaN past the tile's end) over the
-// compacted entries.  Per pair: qh = m/y - 1/2 rounded once (fma),
-// t = rint(qh) is floor(m/y) unless qh lies within QEPS of a half-integer,
-// which the running max of |qh - t| detects; such entries redo the RL_XS
-// pairs with the integer fix-up.  With CHECK, pairs with y > Y_x are skipped
-// (sub-chunks that straddle some x's Y); *cnt counts the pairs taken.
-template <bool CHECK>
+// compacted entries.
+// * FAST (every m < 2^48, every y <= Y): r' = RN(1/y) raised by 4 ulps lies
+//   in [(1/y)(1 + 2^-52), (1/y)(1 + 2^-48.9)], so qd = RN(m r') lies in
+//   (m/y, (m/y)(1 + 2^-48.8)): never below m/y, and above the next integer
+//   only if m/y were within (m/y) 2^-48.8 < 1/y of it, which m mod y >= 0
+//   rules out.  floor(qd) = floor(m/y) exactly: three fp64 ops per pair.
+// * otherwise: qh = m/y - 1/2 rounded once (fma); t = rint(qh) is
+//   floor(m/y) unless qh lies within QEPS of a half-integer, which the
+//   running max of |qh - t| detects; such entries redo the RL_XS pairs with
+//   the integer fix-up.  With YCHECK, pairs with y > Y_x are skipped
+//   (sub-chunks that straddle some x's Y); *cnt counts the pairs taken.
+enum { RL_FAST = 0, RL_NEAR = 1, RL_NEAR_Y = 2 };
+
+template <int MODE>
 __device__ inline void rl_pass(const uint16_t *ent, uint32_t total, uint32_t wb0,
                                const double (&mf)[RL_XS], const uint32_t (&Yv)[RL_XS],
                                const uint64_t *xm, double (&acc)[RL_XS], uint32_t *cnt)
 {
+    constexpr bool YCHECK = MODE == RL_NEAR_Y;
     const uint32_t lane = lane_id();
     for (uint32_t t = lane; t < total; t += 64) {
         const uint32_t e = ent[t];
         const uint32_t y = wb0 + (e & 0x0FFFu);
         const double sg = (e & 0x8000u) ? -1.0 : 1.0;
         const double r = 1.0 / (double)y;
+        if (MODE == RL_FAST) {
+            const double ru = __longlong_as_double(__double_as_longlong(r) + 4);
+#pragma unroll
+            for (int i = 0; i < RL_XS; ++i)
+                acc[i] = fma(sg, floor(mf[i] * ru), acc[i]);
+            continue;
+        }
         double dmax = 0.0;
 #pragma unroll
         for (int i = 0; i < RL_XS; ++i) {
-            if (CHECK && y > Yv[i])
+            if (YCHECK && y > Yv[i])
                 continue;
             const double qh = fma(mf[i], r, -0.5);
             const double tq = rint(qh);
             acc[i] = fma(sg, tq, acc[i]);
             dmax = fmax(dmax, fabs(qh - tq));
-            if (CHECK)
+            if (YCHECK)
                 *cnt += 1;
         }
         if (dmax > 0.5 - QEPS) {
@@ -757,7 +778,7 @@ __device__ inline void rl_pass(const uint16_t *ent, uint32_t total, uint32_t wb0
             __asm__ volatile("" : "+v"(r2));
 #pragma unroll
             for (int i = 0; i < RL_XS; ++i) {
-                if (CHECK && y > Yv[i])
+                if (YCHECK && y > Yv[i])
                     continue;
                 const double qh = fma(mf[i], r2, -0.5);
                 const double tq = rint(qh);
@@ -855,6 +876,7 @@ __device__ inline void mu_item_lanes(const QueryArgs &q, const BlockArgs &b, uin
             double mf[RL_XS], acc[RL_XS];
             uint32_t Yv[RL_XS];
             uint32_t ymin = ~0u;
+            uint64_t mmax = 0;
 #pragma unroll
             for (int i = 0; i < RL_XS; ++i) {
                 const bool ok = (uint32_t)i < nxs;
@@ -865,13 +887,18 @@ __device__ inline void mu_item_lanes(const QueryArgs &q, const BlockArgs &b, uin
                 acc[i] = 0.0;
                 if (ok && Yv[i] < ymin)
                     ymin = Yv[i];
+                mmax = mi > mmax ? mi : mmax;
             }
+            const uint64_t *xm = q.x_m + g0 + xs;
             if (se > ymin) {  // some y of the sub-chunk exceeds some x's Y
                 uint32_t c = 0;
-                rl_pass<true>(ent, total, (uint32_t)sb, mf, Yv, q.x_m + g0 + xs, acc, &c);
+                rl_pass<RL_NEAR_Y>(ent, total, (uint32_t)sb, mf, Yv, xm, acc, &c);
                 nq += c;
             } else {
-                rl_pass<false>(ent, total, (uint32_t)sb, mf, Yv, q.x_m + g0 + xs, acc, nullptr);
+                if (q.rl_fast && (double)mmax < RL_M_EXACT)
+                    rl_pass<RL_FAST>(ent, total, (uint32_t)sb, mf, Yv, xm, acc, nullptr);
+                else
+                    rl_pass<RL_NEAR>(ent, total, (uint32_t)sb, mf, Yv, xm, acc, nullptr);
                 nq += lane == 0 ? (uint64_t)total * nxs : 0;
             }
             // NaN sums of absent x stay on lanes that never write them

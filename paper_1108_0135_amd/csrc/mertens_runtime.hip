@@ -142,8 +142,10 @@ uint64_t auto_u(long double total_n, double scale)
 
 struct Tuning {
     double u_scale = 1.0;  // automatic u = u_scale * (sum of the batch's n)^(2/3)
-    double beta = 0.2;
-    uint32_t ychunk = 4096, kchunk = 2048, klchunk = 256, waves_per_cu = 16;
+    double beta = 0.25;
+    uint32_t ychunk = 16384, kchunk = 1024, klchunk = 256, waves_per_cu = 16;
+    uint32_t sieve_ahead = 4;  // most record slots (blocks sieved ahead of the update)
+    uint32_t rl_fast = 1;
     bool graph = false;  // replay one captured hipGraph per block
 };
 
@@ -219,12 +221,19 @@ struct SieveState {
         return 0;
     }
 
-    int ensure_blocks(uint64_t B)
+    // record buffers for `slots` blocks of length B (a ring: block b uses
+    // slot b mod slots) and their per-slot device parameters
+    uint32_t slots = 1;
+    uint64_t slot_words = 0;  // uint64 per slot
+
+    int ensure_blocks(uint64_t B, uint32_t nslots = 1)
     {
-        RCCHK(ensure(words, B / 64 * 32));
+        RCCHK(ensure(words, (size_t)nslots * (B / 64 * 32)));
+        slots = nslots;
+        slot_words = B / 64 * 4;
         RCCHK(ensure(seg_state, B / SEG * 8));
         RCCHK(ensure(carry, 64));  // M(y1 - 1) at byte 0, segment ticket at byte 8
-        RCCHK(ensure(bp_cur, sizeof(BlockParams)));
+        RCCHK(ensure(bp_cur, (size_t)nslots * sizeof(BlockParams)));
         RCCHK(ensure(bp_index, 64));
         return 0;
     }
@@ -236,10 +245,10 @@ struct SieveState {
                           h_primes.begin());
     }
 
-    BlockArgs make_block(uint64_t y1, uint64_t y2) const
+    BlockArgs make_block(uint64_t y1, uint64_t y2, uint32_t slot = 0) const
     {
         BlockArgs b;
-        b.bp = bp_cur.as<BlockParams>();
+        b.bp = bp_cur.as<BlockParams>() + slot;
         b.y1 = y1;
         b.y2 = y2;
         b.nseg = (uint32_t)((y2 - y1) / SEG + 1);
@@ -251,7 +260,7 @@ struct SieveState {
         b.pres = pres.as<uint2>();
         b.res2 = res2.as<uint64_t>();
         b.pat32 = pattern.as<uint32_t>();
-        b.words = words.as<uint64_t>();
+        b.words = words.as<uint64_t>() + (size_t)slot * slot_words;
         b.seg_state = seg_state.as<uint64_t>();
         b.seg_ticket = reinterpret_cast<uint32_t *>(carry.as<uint8_t>() + 8);
         b.carry = carry.as<int64_t>();
@@ -288,7 +297,7 @@ struct SieveState {
     int sieve(const BlockArgs &b, hipStream_t s, hipEvent_t between, bool set_params = true) const
     {
         if (set_params)
-            HIPCHK(launch_block_set(params_of(b), bp_cur.as<BlockParams>(), s));
+            HIPCHK(launch_block_set(params_of(b), const_cast<BlockParams *>(b.bp), s));
         HIPCHK(launch_block_setup(b, s));
         if (between)
             HIPCHK(hipEventRecord(between, s));
@@ -531,6 +540,7 @@ struct Batch {
         q.ychunk = t.ychunk;
         q.kchunk = t.kchunk;
         q.klchunk = t.klchunk;
+        q.rl_fast = t.rl_fast;
         HIPCHK(launch_zero_u64(pair_stats.as<uint64_t>(), 4, s));
         HIPCHK(launch_plan(q, s));
         return 0;
@@ -622,6 +632,8 @@ struct Ctx {
     int ncu = 256;
     hipStream_t own_stream = nullptr;
     hipStream_t stream = nullptr;
+    hipStream_t sieve_stream = nullptr;             // sieve-ahead (default priority)
+    std::vector<hipEvent_t> sieved_ev, updated_ev;  // per record slot
     uint64_t u_req = 0, block_req = 0;
     Tuning tune;
     size_t serve_capacity = 4096;
@@ -649,6 +661,15 @@ void free_all()
     for (hipEvent_t e : g.events)
         (void)hipEventDestroy(e);
     g.events.clear();
+    for (hipEvent_t e : g.sieved_ev)
+        (void)hipEventDestroy(e);
+    for (hipEvent_t e : g.updated_ev)
+        (void)hipEventDestroy(e);
+    g.sieved_ev.clear();
+    g.updated_ev.clear();
+    if (g.sieve_stream)
+        (void)hipStreamDestroy(g.sieve_stream);
+    g.sieve_stream = nullptr;
     if (g.own_stream)
         (void)hipStreamDestroy(g.own_stream);
     g.own_stream = nullptr;
@@ -679,6 +700,36 @@ float elapsed(size_t a, size_t b)
     return ms;
 }
 
+// Record slots for a sweep of nblocks blocks of length B: at most
+// sieve_ahead, and at most a quarter of the free device memory.
+uint32_t record_slots(uint64_t B, uint64_t nblocks)
+{
+    size_t free_b = 0, total_b = 0;
+    uint64_t cap = g.tune.sieve_ahead;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) {
+        const uint64_t have = g.ss.words.bytes;  // already held (reused)
+        const uint64_t by_mem = (free_b / 4 + have) / (B / 2);
+        cap = std::min<uint64_t>(cap, std::max<uint64_t>(by_mem, 1));
+    }
+    return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(cap, nblocks));
+}
+
+bool slot_events(uint32_t slots)
+{
+    while (g.sieved_ev.size() < slots) {
+        hipEvent_t a, b;
+        if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess)
+            return false;
+        if (hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+            (void)hipEventDestroy(a);
+            return false;
+        }
+        g.sieved_ev.push_back(a);
+        g.updated_ev.push_back(b);
+    }
+    return true;
+}
+
 // The synchronous sweep for nonzero arguments ns[]: fills A on the device
 // and the results into res[] (host).
 int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
@@ -698,17 +749,24 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
     RCCHK(g.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(ymax), 1024)));
     RCCHK(g.ss.ensure_pattern());
     const uint64_t B = choose_block(g.block_req, ymax);
-    RCCHK(g.ss.ensure_blocks(B));
     const uint64_t nblocks = ymax / B + 1;
+    const uint32_t slots = g.tune.graph ? 1u : record_slots(B, nblocks);
+    RCCHK(g.ss.ensure_blocks(B, slots));
     const uint32_t grid = update_grid(g.ncu, g.tune);
 
     size_t ev = 0;
-    if (!event_at(5 * nblocks + 3)) {
+    if (!event_at(5 * nblocks + 3) || !slot_events(slots)) {
         set_error_text("hipEventCreate failed");
         return MERTENS_EIO;
     }
     HIPCHK(hipEventRecord(g.events[ev++], s));
-    RCCHK(g.ss.reset_carry(s));
+    hipStream_t ss = g.sieve_stream;
+    if (g.tune.graph) {
+        RCCHK(g.ss.reset_carry(s));
+    } else {
+        HIPCHK(hipStreamWaitEvent(ss, g.events[0], 0));  // after the plan
+        RCCHK(g.ss.reset_carry(ss));
+    }
     std::vector<size_t> marks;
     marks.reserve(nblocks);
     if (g.tune.graph) {
@@ -747,16 +805,28 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
         (void)hipGraphDestroy(graph);
         HIPCHK(el);
     }
+    // Direct launches: the sieve runs ahead on its own stream into a ring of
+    // record slots, so blocks b+1, b+2, ... are sieved while block b is
+    // updated (block 0 holds most of the update work).  Block b waits for
+    // its sieve; the sieve of block b reuses the slot of block b - slots
+    // once that block's update is done.  The carry between blocks stays in
+    // sieve order on the sieve stream.
     for (uint64_t bi = 0; bi < nblocks && !g.tune.graph; ++bi) {
         const uint64_t y1 = bi * B;
         const uint64_t y2 = std::min(y1 + B - 1, ymax);
-        const BlockArgs b = g.ss.make_block(y1, y2);
+        const uint32_t slot = (uint32_t)(bi % slots);
+        const BlockArgs b = g.ss.make_block(y1, y2, slot);
         marks.push_back(ev);
-        RCCHK(g.ss.sieve(b, s, g.events[ev]));
-        HIPCHK(hipEventRecord(g.events[ev + 1], s));
-        HIPCHK(hipEventRecord(g.events[ev + 2], s));  // (no separate scan pass)
+        if (bi >= slots)
+            HIPCHK(hipStreamWaitEvent(ss, g.updated_ev[slot], 0));
+        RCCHK(g.ss.sieve(b, ss, g.events[ev]));
+        HIPCHK(hipEventRecord(g.events[ev + 1], ss));
+        HIPCHK(hipEventRecord(g.sieved_ev[slot], ss));
+        HIPCHK(hipStreamWaitEvent(s, g.sieved_ev[slot], 0));
+        HIPCHK(hipEventRecord(g.events[ev + 2], s));
         RCCHK(bt.update_block(b, grid, s, g.events[ev + 3]));
         HIPCHK(hipEventRecord(g.events[ev + 4], s));
+        HIPCHK(hipEventRecord(g.updated_ev[slot], s));
         ev += 5;
     }
     HIPCHK(hipEventRecord(g.events[ev], s));
@@ -767,11 +837,13 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
     HIPCHK(hipMemcpyAsync(res.data(), bt.out_dev.p, nq * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(pst, bt.pair_stats.p, 32, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipStreamSynchronize(ss));
 
+    // kernel times per stream; with sieve-ahead they overlap, so their sum
+    // can exceed the total
     double t_sieve = 0, t_scan = 0, t_prep = 0, t_upd = 0;
     for (size_t m : marks) {
         t_sieve += elapsed(m, m + 1);
-        t_scan += elapsed(m + 1, m + 2);
         t_prep += elapsed(m + 2, m + 3);
         t_upd += elapsed(m + 3, m + 4);
     }
@@ -1030,6 +1102,7 @@ int mertens_init(uint64_t u, uint64_t block)
     HIPCHK(hipGetDeviceProperties(&prop, g.device));
     g.ncu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
     HIPCHK(hipStreamCreateWithFlags(&g.own_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&g.sieve_stream, hipStreamNonBlocking));
     g.stream = g.own_stream;
     g.u_req = u;
     g.block_req = block;
@@ -1208,6 +1281,14 @@ int mertens_set_param(const char *key, double value)
         if (!(value >= 64 && value <= (1 << 24)))
             return MERTENS_EINVAL;
         g.tune.kchunk = (uint32_t)value;
+    } else if (!strcmp(key, "rl_fast")) {
+        if (!(value == 0.0 || value == 1.0))
+            return MERTENS_EINVAL;
+        g.tune.rl_fast = (uint32_t)value;
+    } else if (!strcmp(key, "sieve_ahead")) {
+        if (!(value >= 1 && value <= 256))
+            return MERTENS_EINVAL;
+        g.tune.sieve_ahead = (uint32_t)value;
     } else if (!strcmp(key, "klchunk")) {
         if (!(value >= 1 && value <= (1 << 24)))
             return MERTENS_EINVAL;
