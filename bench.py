@@ -19,6 +19,7 @@ Other workloads (``--workload``), reported separately:
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -41,6 +42,28 @@ INT_VALU_PEAK_TOPS = CU * LANES * CLOCK_GHZ / 1000.0  # 39.3 T int32 lane-ops/s
 # full-rate VALU lane-ops: estimate (fp64 multiply), truncate, residual (fma),
 # near-integer offset and test (add, compare), accumulate (add)
 OPS_PER_QUOTIENT = 6
+
+
+def kernel_source_sha256() -> str:
+    """Hash of the kernel sources; counter summaries older than it do not apply."""
+    h = hashlib.sha256()
+    for name in ("mertens_kernels.hip", "mertens_internal.h"):
+        with open(os.path.join(ROOT, "paper_1108_0135_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def traffic_per_launch(kernel: str):
+    """HBM bytes per launch from the committed counter summary, or None if the
+    kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_n1e16_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_sha256") != kernel_source_sha256():
+        return None
+    return d["hbm_bytes_per_launch"]
 
 
 def cpu_baseline(budget_s: float = 15.0) -> dict:
@@ -86,6 +109,8 @@ def workload_default(args, mt) -> dict:
     import torch
 
     mt.init(U_WORK, BLOCK_WORK)
+    ahead = 1 if args.in_turn else 4
+    mt.set_param("sieve_ahead", ahead)
     for _ in range(max(args.warmup, 1)):
         got = int(mt.query([N_WORK])[0])
         if got != EXPECTED:
@@ -107,24 +132,34 @@ def workload_default(args, mt) -> dict:
     def avg(key):
         return sum(s[key] for s in kstats) / len(kstats)
 
-    launches = st["update_launches"]
-    upd_ms_launch = avg("ms_update") / launches
-    sieve_ms_launch = avg("ms_sieve") / st["sieve_launches"]
-    quot = st["rl_quotients"] + st["k_quotients"]
+    # Per-kernel launch times for the roofline: one more query with the sieve
+    # strictly in turn (sieve_ahead = 1), so no kernel's HIP-event interval
+    # includes time shared with the other stream.  Not part of `value`.
+    mt.set_param("sieve_ahead", 1)
+    if int(mt.query([N_WORK])[0]) != EXPECTED:
+        raise RuntimeError("wrong result in the in-turn pass")
+    seq = mt.stats()
+    mt.set_param("sieve_ahead", ahead)
+    launches = seq["update_launches"]
+    upd_ms_launch = seq["ms_update"] / launches
+    sieve_ms_launch = seq["ms_sieve"] / seq["sieve_launches"]
+    quot = seq["rl_quotients"] + seq["k_quotients"]
     upd_tops = quot / launches * OPS_PER_QUOTIENT / (upd_ms_launch * 1e-3) / 1e12
-    # sieve kernels: HBM bytes they must write per y (two 64-bit masks per 64 y)
-    sieve_gbs = (sieved / st["sieve_launches"]) * 0.25 / (sieve_ms_launch * 1e-3) / 1e9
-    if avg("ms_update") >= avg("ms_sieve"):
+    # sieve: record bytes it must write per y (masks and M: 24 of 32 bytes per 64 y)
+    sieve_gbs = (sieved / seq["sieve_launches"]) * 0.375 / (sieve_ms_launch * 1e-3) / 1e9
+    if seq["ms_update"] >= seq["ms_sieve"]:
         roof = {"kernel": "k_update", "bound": "alu", "achieved": upd_tops,
                 "peak": INT_VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": upd_tops / INT_VALU_PEAK_TOPS, "traffic": None,
+                "frac": upd_tops / INT_VALU_PEAK_TOPS, "traffic": traffic_per_launch("k_update"),
                 "avg_launch_ms": upd_ms_launch, "launches": launches,
                 "quotients_per_launch": quot / launches}
     else:
         roof = {"kernel": "k_sieve", "bound": "hbm", "achieved": sieve_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sieve_gbs / HBM_PEAK_GBS,
-                "traffic": None, "avg_launch_ms": sieve_ms_launch,
-                "launches": st["sieve_launches"]}
+                "traffic": traffic_per_launch("k_sieve"), "avg_launch_ms": sieve_ms_launch,
+                "launches": seq["sieve_launches"]}
+    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"
+    roof["in_turn_ms"] = {k: seq[k] for k in ("ms_sieve", "ms_prep", "ms_update", "ms_total")}
     line = {
         "metric": METRIC,
         "value": sieved / (ms_step * 1e-3),
@@ -253,6 +288,8 @@ def main() -> int:
     ap.add_argument("--count", type=int, default=48)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--in-turn", action="store_true",
+                    help="sieve strictly in turn with the update (for per-kernel profiles)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the sweep has no multi-GPU path",

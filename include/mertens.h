@@ -143,6 +143,10 @@ int mertens_set_stream(void *hip_stream);
  *   "sieve_ahead" direct launches: most blocks sieved ahead of the update on
  *                 a second stream, each holding B/2 bytes of records
  *                 (default 4; 1 = strictly in turn)
+ *   "update_window" blocks starting below 2^30 are updated in windows of
+ *                 2^update_window y so that the random M(y) reads of one
+ *                 window stay cache-resident (17..40; default 0: whole
+ *                 blocks)
  *   "rl_fast"     1 (default): run-length quotients with m < 2^48 take the
  *                 test-free rounded-up fp64 floor; 0: always the tested path
  *   "serve_capacity"  most requests in flight for mertens_submit (4096)

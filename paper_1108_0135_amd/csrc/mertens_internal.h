@@ -52,8 +52,8 @@ struct BlockArgs {
     uint2 *pres;              // {p, y1 mod p}: primes >= 5 ascending, residue per block
     uint64_t *res2;           // y1 mod p^2    (per block)
     const uint32_t *pat32;    // pattern bytes as words, length PAT_WORDS
-    // per 64-y word, one 32-byte record: {squarefree bits, mu = -1 bits,
-    // M(y) just before the word's first y (int64), unused}
+    // per 32 y one 16-byte record {mu = +1 bits | mu = -1 bits << 32,
+    // M(y) just before the record's first y (int64)}; 4 uint64 per 64 y
     uint64_t *words;
     // per segment: look-back state of the fused prefix scan, 2-bit flag
     // (1 = segment total, 2 = M(y) at the segment's end) over a 62-bit value

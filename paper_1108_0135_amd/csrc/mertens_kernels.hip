@@ -175,17 +175,28 @@ __device__ inline int64_t wg_exclusive_scan(int64_t v, int64_t *wsum, int64_t &t
     return pre + x - v;
 }
 
-// M(y) for y = y1 + off inside the current block: the word's prefix plus the
-// mu values of the word up to and including bit off mod 64.
+// Records: per 32 consecutive y one 16-byte record {masks, M} with masks =
+// (mu = +1 bits) | (mu = -1 bits) << 32 and M = M(y) just before the
+// record's first y; record r sits at words[2r], words[2r + 1].  One
+// 16-byte load serves any M(y).
 __device__ inline int64_t M_at(const uint64_t *__restrict__ words, uint64_t off)
 {
-    const uint64_t w = off >> 6;
-    const uint32_t b = (uint32_t)(off & 63);
-    const uint64_t lm = (2ull << b) - 1ull;  // bits 0..b (b = 63 wraps to all ones)
-    // one 32-byte record: {squarefree bits, mu = -1 bits, M before the word, -}
-    const ulonglong2 m2 = *reinterpret_cast<const ulonglong2 *>(words + 4 * w);
-    const int64_t mb = (int64_t)words[4 * w + 2];
-    return mb + (int64_t)__popcll(m2.x & lm) - 2 * (int64_t)__popcll(m2.y & lm);
+    const uint64_t r = off >> 5;
+    const uint32_t bt = (uint32_t)(off & 31);
+    const uint32_t lm = (2u << bt) - 1u;  // bits 0..bt (bt = 31 wraps to all ones)
+    const ulonglong2 rec = *reinterpret_cast<const ulonglong2 *>(words + 2 * r);
+    return (int64_t)rec.y + (int64_t)__popc((uint32_t)rec.x & lm) -
+           (int64_t)__popc((uint32_t)(rec.x >> 32) & lm);
+}
+
+// Squarefree and mu = -1 masks of the 64 y of word w (records 2w, 2w + 1).
+__device__ inline void word_masks(const uint64_t *__restrict__ words, uint64_t w, uint64_t &nz,
+                                  uint64_t &ng)
+{
+    const uint64_t a = words[4 * w], c = words[4 * w + 2];
+    const uint64_t pos = (a & 0xFFFFFFFFull) | (c << 32);
+    ng = (a >> 32) | (c & 0xFFFFFFFF00000000ull);
+    nz = pos | ng;
 }
 
 // The block's per-block values, taken from device memory.
@@ -385,9 +396,10 @@ __device__ inline int64_t seg_lookback(const uint64_t *st, uint32_t seg)
 //   A >= floor(log2 y) (fully split) -> mu = (-1)^A
 //   otherwise (one prime > Psieve)   -> mu = -(-1)^A
 // (A's parity is the number of sieving primes dividing y, as every l_p is
-// odd.)  Segments are claimed in ticket order; each writes whole 32-byte
-// records per 64 y (two masks and M(y) before the word), the M(y) prefix
-// coming from a workgroup scan plus a look-back over earlier segments.
+// odd.)  Segments are claimed in ticket order; each writes whole 16-byte
+// records per 32 y (mu = +1 and -1 bits, M(y) before the record), the M(y)
+// prefix coming from a workgroup scan plus a look-back over earlier
+// segments.
 __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
 {
     const BlockArgs b = load_block(b_in);
@@ -552,14 +564,18 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
     }
     __syncthreads();
     const int64_t P = bcast[1];
-    // whole 32-byte records {squarefree bits, mu = -1 bits, M before the word, 0}
+    // two 16-byte records per word: {+1 bits | -1 bits << 32, M before}
     const uint64_t gw0 = (uint64_t)seg * SEG_WORDS + tid;
-    ulonglong2 *r0 = reinterpret_cast<ulonglong2 *>(b.words + 4 * gw0);
-    r0[0] = make_ulonglong2(nzw[0], ngw[0]);
-    r0[1] = make_ulonglong2((uint64_t)(P + ex0), 0ull);
-    ulonglong2 *r1 = reinterpret_cast<ulonglong2 *>(b.words + 4 * (gw0 + SIEVE_THREADS));
-    r1[0] = make_ulonglong2(nzw[1], ngw[1]);
-    r1[1] = make_ulonglong2((uint64_t)(P + tot0 + ex1), 0ull);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint64_t neg = ngw[h], pos = nzw[h] & ~neg;
+        const int64_t mw = P + (h ? tot0 + ex1 : ex0);
+        const int64_t mh = mw + (int64_t)__popc((uint32_t)pos) - (int64_t)__popc((uint32_t)neg);
+        ulonglong2 *r = reinterpret_cast<ulonglong2 *>(
+            b.words + 4 * (gw0 + (uint64_t)h * SIEVE_THREADS));
+        r[0] = make_ulonglong2((pos & 0xFFFFFFFFull) | (neg << 32), (uint64_t)mw);
+        r[1] = make_ulonglong2((pos >> 32) | (neg & 0xFFFFFFFF00000000ull), (uint64_t)mh);
+    }
 }
 
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s)
@@ -840,12 +856,11 @@ __device__ inline void mu_item_lanes(const QueryArgs &q, const BlockArgs &b, uin
         uint64_t bits = 0, ngw = 0;
         if (lane < nw) {
             const uint64_t wbase = sb + 64ull * lane;
-            const ulonglong2 m2 =
-                *reinterpret_cast<const ulonglong2 *>(b.words + 4 * ((wbase - b.y1) >> 6));
+            uint64_t nzm;
+            word_masks(b.words, (wbase - b.y1) >> 6, nzm, ngw);
             const uint32_t lob = wbase < ss ? (uint32_t)(ss - wbase) : 0u;
             const uint32_t hib = (se - wbase) < 63 ? (uint32_t)(se - wbase) : 63u;
-            bits = m2.x & (~0ull << lob) & ((2ull << hib) - 1ull);
-            ngw = m2.y;
+            bits = nzm & (~0ull << lob) & ((2ull << hib) - 1ull);
         }
         const uint32_t cnt = (uint32_t)__popcll(bits);
         uint32_t incl = cnt;
@@ -953,8 +968,10 @@ __device__ inline void mu_item(const QueryArgs &q, const BlockArgs &b, uint32_t 
     double accf = 0.0;  // integer-valued, |accf| < ychunk * 2^32 <= 2^52
     for (uint64_t wbase = cs & ~63ull; wbase <= ce; wbase += 64) {
         const uint64_t woff = (wbase - b.y1) >> 6;
-        const uint64_t nz = uniform_u64(b.words[4 * woff]);
-        const uint64_t ng = uniform_u64(b.words[4 * woff + 1]);
+        uint64_t nzv, ngv;
+        word_masks(b.words, woff, nzv, ngv);
+        const uint64_t nz = uniform_u64(nzv);
+        const uint64_t ng = uniform_u64(ngv);
         const uint32_t lob = wbase < cs ? (uint32_t)(cs - wbase) : 0u;
         const uint32_t hib = (ce - wbase) < 63 ? (uint32_t)(ce - wbase) : 63u;
         uint64_t bits = nz & (~0ull << lob) & ((2ull << hib) - 1ull);
@@ -1059,21 +1076,16 @@ __device__ inline uint64_t M_sum_masked(const uint64_t *__restrict__ words,
                                         const uint64_t (&off)[K_UNROLL],
                                         const bool (&act)[K_UNROLL])
 {
-    ulonglong2 m2[K_UNROLL];
-    uint64_t mb[K_UNROLL];
+    ulonglong2 rec[K_UNROLL];
 #pragma unroll
-    for (int u = 0; u < K_UNROLL; ++u) {
-        const uint64_t w = off[u] >> 6;
-        m2[u] = *reinterpret_cast<const ulonglong2 *>(words + 4 * w);
-        mb[u] = words[4 * w + 2];
-    }
+    for (int u = 0; u < K_UNROLL; ++u)
+        rec[u] = *reinterpret_cast<const ulonglong2 *>(words + 2 * (off[u] >> 5));
     uint64_t s = 0;
 #pragma unroll
     for (int u = 0; u < K_UNROLL; ++u) {
-        const uint32_t bt = (uint32_t)(off[u] & 63);
-        const uint64_t lm = (2ull << bt) - 1ull;
-        const uint64_t v = mb[u] + (uint64_t)__popcll(m2[u].x & lm) -
-                           2ull * (uint64_t)__popcll(m2[u].y & lm);
+        const uint32_t lm = (2u << (uint32_t)(off[u] & 31)) - 1u;
+        const uint64_t v = rec[u].y + (uint64_t)__popc((uint32_t)rec[u].x & lm) -
+                           (uint64_t)__popc((uint32_t)(rec[u].x >> 32) & lm);
         s += act[u] ? v : 0ull;
     }
     return s;
@@ -1484,7 +1496,8 @@ __global__ void k_debug_mu(BlockArgs b_in, uint64_t y_first, uint32_t count, int
     const uint64_t off = y_first + i - b.y1;
     const uint64_t w = off >> 6;
     const uint32_t bt = (uint32_t)(off & 63);
-    const uint64_t nz = b.words[4 * w], ng = b.words[4 * w + 1];
+    uint64_t nz, ng;
+    word_masks(b.words, w, nz, ng);
     mu[i] = ((nz >> bt) & 1) ? (((ng >> bt) & 1) ? -1 : 1) : 0;
     if (mert)
         mert[i] = M_at(b.words, off);

@@ -145,6 +145,11 @@ struct Tuning {
     double beta = 0.25;
     uint32_t ychunk = 16384, kchunk = 1024, klchunk = 256, waves_per_cu = 16;
     uint32_t sieve_ahead = 4;  // most record slots (blocks sieved ahead of the update)
+    // blocks starting below window_ymax are updated in windows of
+    // 2^update_window y, so the records that the explicit-k gathers of one
+    // window touch stay cache-resident (0: whole blocks)
+    uint32_t update_window = 0;
+    uint64_t window_ymax = 1ull << 30;
     uint32_t rl_fast = 1;
     bool graph = false;  // replay one captured hipGraph per block
 };
@@ -222,7 +227,9 @@ struct SieveState {
     }
 
     // record buffers for `slots` blocks of length B (a ring: block b uses
-    // slot b mod slots) and their per-slot device parameters
+    // slot b mod slots) and their per-slot device parameters, followed by
+    // the parameters of up to MAX_WINDOWS update windows
+    static constexpr uint32_t MAX_WINDOWS = 64;
     uint32_t slots = 1;
     uint64_t slot_words = 0;  // uint64 per slot
 
@@ -233,7 +240,7 @@ struct SieveState {
         slot_words = B / 64 * 4;
         RCCHK(ensure(seg_state, B / SEG * 8));
         RCCHK(ensure(carry, 64));  // M(y1 - 1) at byte 0, segment ticket at byte 8
-        RCCHK(ensure(bp_cur, (size_t)nslots * sizeof(BlockParams)));
+        RCCHK(ensure(bp_cur, ((size_t)nslots + MAX_WINDOWS) * sizeof(BlockParams)));
         RCCHK(ensure(bp_index, 64));
         return 0;
     }
@@ -265,6 +272,18 @@ struct SieveState {
         b.seg_ticket = reinterpret_cast<uint32_t *>(carry.as<uint8_t>() + 8);
         b.carry = carry.as<int64_t>();
         return b;
+    }
+
+    // Update window [ua, ub] (ua a multiple of 64) of block b: the same
+    // records, addressed from ua, with its own device parameters.
+    BlockArgs window_of(const BlockArgs &b, uint64_t ua, uint64_t ub, uint32_t w) const
+    {
+        BlockArgs v = b;
+        v.words = b.words + (ua - b.y1) / 64 * 4;
+        v.y1 = ua;
+        v.y2 = ub;
+        v.bp = bp_cur.as<BlockParams>() + slots + w;
+        return v;
     }
 
     static BlockParams params_of(const BlockArgs &b)
@@ -824,7 +843,19 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
         HIPCHK(hipEventRecord(g.sieved_ev[slot], ss));
         HIPCHK(hipStreamWaitEvent(s, g.sieved_ev[slot], 0));
         HIPCHK(hipEventRecord(g.events[ev + 2], s));
-        RCCHK(bt.update_block(b, grid, s, g.events[ev + 3]));
+        const uint64_t W = g.tune.update_window ? (1ull << g.tune.update_window) : 0;
+        if (W && y1 < g.tune.window_ymax && y2 - y1 >= W &&
+            (y2 - y1) / W < SieveState::MAX_WINDOWS) {
+            uint32_t w = 0;
+            for (uint64_t ua = y1; ua <= y2; ua += W, ++w) {
+                const BlockArgs bw = g.ss.window_of(b, ua, std::min(ua + W - 1, y2), w);
+                HIPCHK(launch_block_set(SieveState::params_of(bw),
+                                        const_cast<BlockParams *>(bw.bp), s));
+                RCCHK(bt.update_block(bw, grid, s, w == 0 ? g.events[ev + 3] : nullptr));
+            }
+        } else {
+            RCCHK(bt.update_block(b, grid, s, g.events[ev + 3]));
+        }
         HIPCHK(hipEventRecord(g.events[ev + 4], s));
         HIPCHK(hipEventRecord(g.updated_ev[slot], s));
         ev += 5;
@@ -1285,6 +1316,10 @@ int mertens_set_param(const char *key, double value)
         if (!(value == 0.0 || value == 1.0))
             return MERTENS_EINVAL;
         g.tune.rl_fast = (uint32_t)value;
+    } else if (!strcmp(key, "update_window")) {
+        if (!(value == 0.0 || (value >= 17 && value <= 40)) || value != (double)(int)value)
+            return MERTENS_EINVAL;
+        g.tune.update_window = (uint32_t)value;
     } else if (!strcmp(key, "sieve_ahead")) {
         if (!(value >= 1 && value <= 256))
             return MERTENS_EINVAL;
