@@ -42,6 +42,7 @@ INT_VALU_PEAK_TOPS = CU * LANES * CLOCK_GHZ / 1000.0  # 39.3 T int32 lane-ops/s
 # full-rate VALU lane-ops: estimate (fp64 multiply), truncate, residual (fma),
 # near-integer offset and test (add, compare), accumulate (add)
 OPS_PER_QUOTIENT = 6
+RECORD_BYTES = 16  # one sieve record: M(y) checkpoint and mu bits of 32 y
 
 
 def kernel_source_sha256() -> str:
@@ -145,20 +146,30 @@ def workload_default(args, mt) -> dict:
     sieve_ms_launch = seq["ms_sieve"] / seq["sieve_launches"]
     quot = seq["rl_quotients"] + seq["k_quotients"]
     upd_tops = quot / launches * OPS_PER_QUOTIENT / (upd_ms_launch * 1e-3) / 1e12
-    # sieve: record bytes it must write per y (masks and M: 24 of 32 bytes per 64 y)
-    sieve_gbs = (sieved / seq["sieve_launches"]) * 0.375 / (sieve_ms_launch * 1e-3) / 1e9
+    # update: algorithmic HBM bytes = one 16-byte record per explicit-k pair
+    # (a random M(y) read) + the run-length masks (8 bytes per 32 y) read once
+    # per 64-x tile over y <= Y
+    upd_bytes = (RECORD_BYTES * seq["k_quotients"] + 0.25 * seq["sum_Y"] / 64) / launches
+    upd_gbs = upd_bytes / (upd_ms_launch * 1e-3) / 1e9
+    # sieve: the records it writes, 0.5 byte per y
+    sieve_gbs = (sieved / seq["sieve_launches"]) * 0.5 / (sieve_ms_launch * 1e-3) / 1e9
     if seq["ms_update"] >= seq["ms_sieve"]:
-        roof = {"kernel": "k_update", "bound": "alu", "achieved": upd_tops,
-                "peak": INT_VALU_PEAK_TOPS, "unit": "Tops/s",
-                "frac": upd_tops / INT_VALU_PEAK_TOPS, "traffic": traffic_per_launch("k_update"),
+        roof = {"kernel": "k_update", "bound": "hbm", "achieved": upd_gbs,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": upd_gbs / HBM_PEAK_GBS,
+                "traffic": traffic_per_launch("k_update"),
+                "algorithmic_bytes_per_launch": upd_bytes,
                 "avg_launch_ms": upd_ms_launch, "launches": launches,
-                "quotients_per_launch": quot / launches}
+                "quotients_per_launch": quot / launches,
+                "alu_view": {"achieved_Tops": upd_tops, "peak_Tops": INT_VALU_PEAK_TOPS,
+                             "frac": upd_tops / INT_VALU_PEAK_TOPS,
+                             "ops_per_quotient": OPS_PER_QUOTIENT}}
     else:
         roof = {"kernel": "k_sieve", "bound": "hbm", "achieved": sieve_gbs,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sieve_gbs / HBM_PEAK_GBS,
                 "traffic": traffic_per_launch("k_sieve"), "avg_launch_ms": sieve_ms_launch,
                 "launches": seq["sieve_launches"]}
-    roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)"
+    roof["traffic_unit"] = ("bytes per launch between L2 and memory (rocprofv3 FETCH_SIZE x2 + "
+                            "WRITE_SIZE x1, calibrated on a plain copy)")
     roof["in_turn_ms"] = {k: seq[k] for k in ("ms_sieve", "ms_prep", "ms_update", "ms_total")}
     line = {
         "metric": METRIC,
