@@ -128,7 +128,9 @@ int mertens_set_stream(void *hip_stream);
 
 /*
  * mertens_set_param -- tuning knobs (results never depend on them).
- *   "u_scale"     automatic u = u_scale * (sum of the batch's n)^(2/3); default 1
+ *   "u_scale"     automatic u = u_scale * (sum of the batch's n)^(2/3), where
+ *                 n within a relative 2^-20 of each other count once (they
+ *                 share their update work); default 0.5
  *   "beta"        split of the per-x sum between the run-length part over
  *                 y <= Y and the explicit k part (K = floor(beta*sqrt(m))),
  *                 in (0, 1]; default 0.25

@@ -28,10 +28,10 @@ from . import mertens as mt
 ARCH = os.environ.get("MERTENS_OFFLOAD_ARCH", "gfx950")
 TUNED_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), f"tuned_{ARCH}.json")
 
-DEFAULTS = {"beta": 0.25, "u_scale": 1.0, "ychunk": 16384, "kchunk": 1024}
+DEFAULTS = {"beta": 0.25, "u_scale": 0.5, "ychunk": 16384, "kchunk": 1024}
 SPACE = {
     "beta": [0.15, 0.2, 0.25, 0.3, 0.4],
-    "u_scale": [0.6, 0.8, 1.0, 1.25, 1.6],
+    "u_scale": [0.3, 0.4, 0.5, 0.65, 0.8, 1.0],
     "ychunk": [4096, 8192, 16384, 32768],
     "kchunk": [512, 1024, 2048],
 }

@@ -133,6 +133,25 @@ uint8_t log_prime_host(uint64_t p)
 // proportional to (sum of n)/sqrt(u), the total is smallest at u ~ (sum n)^(2/3)
 // (Section 2, and its remark on several close values of n); the scale is
 // the tuned ratio of the two costs.
+// Sum of n over clusters of nearly equal n (consecutive sorted values within
+// a relative 2^-20 of the cluster's first): such queries share L and one
+// keyed set of entries, so their update costs about one query's.
+long double effective_total_n(std::vector<uint64_t> v)
+{
+    std::sort(v.begin(), v.end());
+    long double sum = 0;
+    size_t i = 0;
+    while (i < v.size()) {
+        const uint64_t start = v[i];
+        size_t j = i + 1;
+        while (j < v.size() && v[j] - start <= (start >> 20))
+            ++j;
+        sum += (long double)v[j - 1];
+        i = j;
+    }
+    return sum;
+}
+
 uint64_t auto_u(long double total_n, double scale)
 {
     const double v = scale * std::pow((double)total_n, 2.0 / 3.0);
@@ -141,7 +160,7 @@ uint64_t auto_u(long double total_n, double scale)
 }
 
 struct Tuning {
-    double u_scale = 1.0;  // automatic u = u_scale * (sum of the batch's n)^(2/3)
+    double u_scale = 0.5;  // automatic u = u_scale * (clustered sum of the batch's n)^(2/3)
     double beta = 0.25;
     uint32_t ychunk = 16384, kchunk = 1024, klchunk = 256, waves_per_cu = 16;
     uint32_t sieve_ahead = 4;  // most record slots (blocks sieved ahead of the update)
@@ -755,12 +774,8 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
 {
     const size_t nq = ns.size();
     uint64_t u = g.u_req;
-    if (u == 0) {
-        long double sum = 0;
-        for (uint64_t v : ns)
-            sum += (long double)v;
-        u = auto_u(sum, g.tune.u_scale);
-    }
+    if (u == 0)
+        u = auto_u(effective_total_n(ns), g.tune.u_scale);
     hipStream_t s = g.stream;
     Batch &bt = g.batch;
     RCCHK(bt.plan(ns, std::vector<uint64_t>(nq, u), g.tune, s));

@@ -51,6 +51,14 @@ def main() -> None:
     out["window1e12"] = {"seed": 2, "n": [int(v) for v in nw],
                          "M": [o2.query(int(v))[0] for v in nw]}
 
+    # the dense window at full size (n0 from seed 0 in [1e18, 1.8e19]): the
+    # differences M(n_{i+1}) - M(n_i) = sum of mu over (n_i, n_{i+1}], i < 7
+    # (O1 on the window; the M(n_i) themselves are beyond the oracle)
+    nd = [int(v) for v in inputs.dense_window(seed=0, count=8)]
+    mu = oracle.mu_range(nd[0] + 1, nd[-1])
+    diffs = [int(mu[nd[i] - nd[0]:nd[i + 1] - nd[0]].astype(np.int64).sum()) for i in range(7)]
+    out["window1e19_diffs"] = {"seed": 0, "n": nd, "diffs": diffs}
+
     path = os.path.join(HERE, "golden.json")
     with open(path, "w") as f:
         json.dump(out, f)

@@ -235,3 +235,17 @@ def test_window_keyed_matches_plain(mt):
             assert np.array_equal(mt.byproducts(0), byp[(0, 5, 15).index(i)])
     assert got == alone
     assert np.array_equal(byp[3], byp[0])
+
+
+def test_window1e19_full_size_differences(mt):
+    # the dense-window workload at its real size: 8 consecutive n_i = n0 +
+    # 997 i with n0 ~ 1.18e19 as one keyed group; the M(n_i) are beyond the
+    # oracle, but their differences are sums of mu over (n_i, n_{i+1}], which
+    # the oracle computed (golden), and member 0 must equal the plain path
+    _reinit(mt)
+    g = GOLDEN["window1e19_diffs"]
+    ns = [int(v) for v in inputs.dense_window(seed=g["seed"], count=8)]
+    assert ns == g["n"]
+    got = [int(v) for v in mt.query(ns)]
+    assert [got[i + 1] - got[i] for i in range(7)] == g["diffs"]
+    assert int(mt.query([ns[0]])[0]) == got[0]
