@@ -13,16 +13,19 @@ constexpr uint32_t SEG = 1u << 17;
 constexpr uint32_t SEG_WORDS = SEG / 64;     // 64-y mask words per segment
 constexpr int SIEVE_THREADS = 1024;          // 16 waves, 2 mask words per thread
 // Pre-sieved pattern: log sums of 2,3,5,7,11,13 and square flags of 4 and 9
-// repeat with period lcm(2,3,5,7,11,13,4,9) = 180180.
+// repeat with period lcm(2,3,5,7,11,13,4,9) = 180180.  Four copies shifted
+// by 0, 4, 8, 12 bytes let every segment copy it with 16-byte loads.
 constexpr uint32_t PAT = 180180;
-constexpr uint32_t PAT_WORDS = (PAT + SEG) / 4 + 16;
+constexpr uint32_t PAT_WORDS = ((PAT + SEG) / 4 + 16 + 3) & ~3u;  // uint32 per copy
 // Sieving primes below this bound (>= 64 multiples per segment) are walked by
 // a whole wavefront, lane i taking the i-th multiple; larger ones by one lane.
 constexpr uint32_t SMALL_P = SEG / 64;
 // Squares of primes up to this bound are flagged in LDS by whole wavefronts;
-// a larger square (> 2^20 > SEG) meets a segment at most once and is placed
-// by one lane per prime.
+// a larger square (> 2^20 > SEG) meets a segment at most once: per block,
+// one thread per prime lists its multiples in per-segment buckets of
+// SQ_BUCKET entries (a segment whose bucket overflows scans every prime).
 constexpr uint32_t SQ_LDS_P = 1024;
+constexpr uint32_t SQ_BUCKET = 64;
 // First index of the prime table that is sieved (table starts at 5; the
 // pattern covers 5, 7, 11, 13, so sieving starts at 17 = index 4).
 constexpr uint32_t FIRST_SIEVED = 4;
@@ -36,6 +39,7 @@ constexpr int UPD_THREADS = 256;             // 4 independent waves per workgrou
 struct BlockParams {
     uint64_t y1, y2;
     uint32_t nseg, n_sq, n_sq_lds, pat_off;
+    uint32_t n_sieve, pad;
 };
 
 // One y-block [y1, y2] of the sweep.  The scalar fields below mirror *bp on
@@ -45,7 +49,7 @@ struct BlockArgs {
     uint64_t y1, y2;
     uint32_t nseg;
     uint32_t n_small;   // primes with index in [FIRST_SIEVED, n_small) are < SMALL_P
-    uint32_t n_sieve;   // primes with index < n_sieve are sieved (all p <= Psieve)
+    uint32_t n_sieve;   // primes with index < n_sieve are sieved (p <= max(sqrt(y2), SMALL_P))
     uint32_t n_sq_lds;  // primes with index < n_sq_lds have p <= SQ_LDS_P
     uint32_t n_sq;      // primes with index < n_sq have p^2 <= y2
     uint32_t pat_off;   // y1 mod PAT
@@ -59,6 +63,8 @@ struct BlockArgs {
     // (1 = segment total, 2 = M(y) at the segment's end) over a 62-bit value
     uint64_t *seg_state;
     uint32_t *seg_ticket;     // segments are claimed in ticket order
+    uint32_t *sq_cnt;         // per segment: large-square hits listed (may exceed SQ_BUCKET)
+    uint32_t *sq_buf;         // per segment: SQ_BUCKET offsets of large-square multiples
     int64_t *carry;           // M(y1 - 1), advanced by the block's last segment
 };
 
@@ -105,6 +111,7 @@ hipError_t launch_block_next(const BlockParams *table, BlockParams *cur, uint32_
                              hipStream_t s);
 hipError_t launch_plan(const QueryArgs &q, hipStream_t s);
 hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s);
+hipError_t launch_square_buckets(const BlockArgs &b, hipStream_t s);
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s);
 hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
 hipError_t launch_scan_items(const QueryArgs &q, hipStream_t s);

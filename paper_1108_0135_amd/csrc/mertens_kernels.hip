@@ -209,6 +209,7 @@ __device__ inline BlockArgs load_block(BlockArgs b)
     b.n_sq = p.n_sq;
     b.n_sq_lds = p.n_sq_lds;
     b.pat_off = p.pat_off;
+    b.n_sieve = p.n_sieve;
     return b;
 }
 
@@ -329,8 +330,10 @@ __global__ void k_block_setup(BlockArgs b_in)
     const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0)
         *b.seg_ticket = 0;
-    if (i < b.nseg)
+    if (i < b.nseg) {
         b.seg_state[i] = 0;
+        b.sq_cnt[i] = 0;
+    }
     if (i >= b.n_sieve)
         return;
     const uint64_t p = b.pres[i].x;
@@ -343,6 +346,37 @@ hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s)
 {
     const uint32_t n = (b.n_sieve > b.nseg ? b.n_sieve : b.nseg) + 1;
     hipLaunchKernelGGL(k_block_setup, dim3((n + 255) / 256), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+// Large squares: one wave per prime p (SQ_LDS_P < p, p^2 <= y2), lane j
+// taking multiples j, j + 64, ... of p^2 in the block (at most B / 2^20 + 1
+// of them), lists every multiple in its segment's bucket.
+__global__ void k_square_buckets(BlockArgs b_in)
+{
+    const BlockArgs b = load_block(b_in);
+    const uint32_t i = b.n_sq_lds + __builtin_amdgcn_readfirstlane(
+                                        blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    if (i >= b.n_sq)
+        return;
+    const uint64_t p = b.pres[i].x;
+    const uint64_t d = p * p;
+    const uint64_t r2 = b.res2[i];
+    const uint64_t span = b.y2 - b.y1;
+    for (uint64_t o = (r2 ? d - r2 : 0) + lane_id() * d; o <= span; o += 64 * d) {
+        const uint32_t sg = (uint32_t)(o / SEG);
+        const uint32_t k = atomicAdd(&b.sq_cnt[sg], 1u);
+        if (k < SQ_BUCKET)
+            b.sq_buf[(uint64_t)sg * SQ_BUCKET + k] = (uint32_t)(o % SEG);
+    }
+}
+
+hipError_t launch_square_buckets(const BlockArgs &b, hipStream_t s)
+{
+    if (b.n_sq <= b.n_sq_lds)
+        return hipSuccess;
+    const uint32_t n = b.n_sq - b.n_sq_lds;  // waves
+    hipLaunchKernelGGL(k_square_buckets, dim3((n + 3) / 4), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 
@@ -422,9 +456,13 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
     uint32_t po = b.pat_off + segbase % PAT;
     if (po >= PAT)
         po -= PAT;
-    const uint32_t *src = b.pat32 + (po >> 2);  // po is a multiple of 4
-    for (uint32_t j = tid; j < SEG / 4; j += SIEVE_THREADS)
-        lds[j] = src[j];
+    // po is a multiple of 4: copy (po / 4) mod 4 starts 4 (po / 4 mod 4) bytes
+    // later, so the segment's bytes start 16-byte aligned in it
+    const uint4 *src = reinterpret_cast<const uint4 *>(
+        b.pat32 + (size_t)((po >> 2) & 3u) * PAT_WORDS + ((po >> 2) & ~3u));
+    uint4 *l4w = reinterpret_cast<uint4 *>(lds);
+    for (uint32_t j = tid; j < SEG / 16; j += SIEVE_THREADS)
+        l4w[j] = src[j];
     __syncthreads();
 
     // squares p^2 <= SQ_LDS_P^2: one wave per prime, lane i takes multiple i
@@ -473,11 +511,19 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
                 atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
         }
     }
-    // squares p^2 > SQ_LDS_P^2 (> SEG): at most one multiple in the segment.
-    // f = offset of the block's first multiple; the segment's first is
-    // f - segbase mod p^2, with the quotient estimated in fp32 (t < 2^31,
-    // error < 1) and corrected once.
-    for (uint32_t i = b.n_sq_lds + tid; i < b.n_sq; i += SIEVE_THREADS) {
+    // squares p^2 > SQ_LDS_P^2 (> SEG): at most one multiple each in the
+    // segment, listed in its bucket.  Should the bucket have overflowed,
+    // every such prime is checked here instead: f = offset of the block's
+    // first multiple; the segment's first is f - segbase mod p^2, with the
+    // quotient estimated in fp32 (t < 2^31, error < 1) and corrected once.
+    const uint32_t nsq = b.sq_cnt[seg];
+    if (nsq <= SQ_BUCKET) {
+        for (uint32_t k = tid; k < nsq; k += SIEVE_THREADS) {
+            const uint32_t o = b.sq_buf[(uint64_t)seg * SQ_BUCKET + k];
+            atomicOr(&lds[o >> 2], 0x80u << ((o & 3u) << 3));
+        }
+    }
+    for (uint32_t i = b.n_sq_lds + tid; nsq > SQ_BUCKET && i < b.n_sq; i += SIEVE_THREADS) {
         const uint64_t p = b.pres[i].x;
         const uint64_t d = p * p;
         const uint64_t r2 = b.res2[i];
@@ -508,6 +554,11 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
         const uint32_t w = tid + (uint32_t)h * SIEVE_THREADS;
         const uint64_t ybase = s0 + (uint64_t)w * 64;
         const uint4 *l4 = reinterpret_cast<const uint4 *>(lds) + w * 4;
+        // floor(log2 y) is the same for the 64 y of a word (a power of two
+        // >= 64 only ever starts a word); only the block's first word, y < 64,
+        // takes it per group of 4 (y < 4 is patched below)
+        const uint32_t Tw = 63u - (uint32_t)__clzll((long long)(ybase | 1));
+        const bool low = ybase < 64;
         uint64_t nz = 0, ng = 0;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
@@ -516,10 +567,8 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
 #pragma unroll
             for (int g4 = 0; g4 < 4; ++g4) {
                 const uint32_t g = (uint32_t)(j * 4 + g4);
-                const uint64_t y = ybase + 4 * g;
-                // floor(log2 y) of the group's first y; the group's 4 y
-                // share it (y is a multiple of 4); y < 4 is patched below
-                const uint32_t T = 63u - (uint32_t)__clzll((long long)(y | 1));
+                const uint32_t T =
+                    low ? 63u - (uint32_t)__clzll((long long)((ybase + 4 * g) | 1)) : Tw;
                 const uint32_t x = vs[g4];
                 const uint32_t F = ((x & 0x7f7f7f7fu) + (128u - T) * 0x01010101u) & 0x80808080u;
                 const uint32_t par = (x & 0x01010101u) << 7;

@@ -179,12 +179,13 @@ struct Tuning {
 struct SieveState {
     uint64_t psieve = 0;
     std::vector<uint32_t> h_primes;  // primes >= 5 up to psieve
-    DevBuf pres, res2, pattern, words, seg_state, carry, bp_cur, bp_table, bp_index;
+    DevBuf pres, res2, pattern, words, seg_state, sq_cnt, sq_buf, carry, bp_cur, bp_table,
+        bp_index;
     bool have_pattern = false;
 
     void release()
     {
-        DevBuf *bufs[] = {&pres, &res2, &pattern, &words, &seg_state, &carry,
+        DevBuf *bufs[] = {&pres, &res2, &pattern, &words, &seg_state, &sq_cnt, &sq_buf, &carry,
                           &bp_cur, &bp_table, &bp_index};
         for (DevBuf *b : bufs)
             b->release();
@@ -222,15 +223,18 @@ struct SieveState {
 
     // Pattern of the modified sieve for the primes 2, 3, 5, 7, 11, 13 and the
     // squares 4, 9 (period 180180), extended by one segment so a segment's
-    // initial state is one straight copy.
+    // initial state is one straight copy, in four copies shifted by 0, 4, 8,
+    // 12 bytes so that copy is 16-byte aligned.
     int ensure_pattern()
     {
         if (have_pattern)
             return 0;
         const uint32_t small[6] = {2, 3, 5, 7, 11, 13};
-        std::vector<uint8_t> pat((size_t)PAT_WORDS * 4, 0);
+        // four copies; copy c starts at pattern byte 4c
+        std::vector<uint8_t> pat((size_t)PAT_WORDS * 4 * 4, 0);
         for (size_t i = 0; i < pat.size(); ++i) {
-            const uint32_t r = (uint32_t)(i % PAT);
+            const size_t c = i / ((size_t)PAT_WORDS * 4), j = i % ((size_t)PAT_WORDS * 4);
+            const uint32_t r = (uint32_t)((4 * c + j) % PAT);
             uint32_t a = 0;
             for (uint32_t p : small)
                 if (r % p == 0)
@@ -258,6 +262,8 @@ struct SieveState {
         slots = nslots;
         slot_words = B / 64 * 4;
         RCCHK(ensure(seg_state, B / SEG * 8));
+        RCCHK(ensure(sq_cnt, B / SEG * 4));
+        RCCHK(ensure(sq_buf, B / SEG * SQ_BUCKET * 4));
         RCCHK(ensure(carry, 64));  // M(y1 - 1) at byte 0, segment ticket at byte 8
         RCCHK(ensure(bp_cur, ((size_t)nslots + MAX_WINDOWS) * sizeof(BlockParams)));
         RCCHK(ensure(bp_index, 64));
@@ -279,7 +285,8 @@ struct SieveState {
         b.y2 = y2;
         b.nseg = (uint32_t)((y2 - y1) / SEG + 1);
         b.n_small = count_primes_upto(SMALL_P - 1);
-        b.n_sieve = (uint32_t)h_primes.size();
+        // primes up to sqrt(y2) decide mu on the block (and every p < SMALL_P)
+        b.n_sieve = count_primes_upto(std::max<uint64_t>(ceil_sqrt_host(y2), SMALL_P));
         b.n_sq = count_primes_upto(isqrt_host(y2));
         b.n_sq_lds = std::min(count_primes_upto(SQ_LDS_P), b.n_sq);
         b.pat_off = (uint32_t)(y1 % PAT);
@@ -288,6 +295,8 @@ struct SieveState {
         b.pat32 = pattern.as<uint32_t>();
         b.words = words.as<uint64_t>() + (size_t)slot * slot_words;
         b.seg_state = seg_state.as<uint64_t>();
+        b.sq_cnt = sq_cnt.as<uint32_t>();
+        b.sq_buf = sq_buf.as<uint32_t>();
         b.seg_ticket = reinterpret_cast<uint32_t *>(carry.as<uint8_t>() + 8);
         b.carry = carry.as<int64_t>();
         return b;
@@ -314,6 +323,8 @@ struct SieveState {
         p.n_sq = b.n_sq;
         p.n_sq_lds = b.n_sq_lds;
         p.pat_off = b.pat_off;
+        p.n_sieve = b.n_sieve;
+        p.pad = 0;
         return p;
     }
 
@@ -325,6 +336,7 @@ struct SieveState {
         b.nseg = (uint32_t)(B / SEG);
         b.n_sq_lds = 0;
         b.n_sq = (uint32_t)h_primes.size();
+        b.n_sieve = (uint32_t)h_primes.size();
         return b;
     }
 
@@ -337,6 +349,7 @@ struct SieveState {
         if (set_params)
             HIPCHK(launch_block_set(params_of(b), const_cast<BlockParams *>(b.bp), s));
         HIPCHK(launch_block_setup(b, s));
+        HIPCHK(launch_square_buckets(b, s));
         if (between)
             HIPCHK(hipEventRecord(between, s));
         HIPCHK(launch_sieve(b, s));
@@ -794,13 +807,13 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
         return MERTENS_EIO;
     }
     HIPCHK(hipEventRecord(g.events[ev++], s));
-    hipStream_t ss = g.sieve_stream;
-    if (g.tune.graph) {
-        RCCHK(g.ss.reset_carry(s));
-    } else {
+    // one record slot: everything in turn on one stream (no cross-stream
+    // waits between the sieve and the update of a block)
+    const bool ahead = !g.tune.graph && slots > 1;
+    hipStream_t ss = ahead ? g.sieve_stream : s;
+    if (ahead)
         HIPCHK(hipStreamWaitEvent(ss, g.events[0], 0));  // after the plan
-        RCCHK(g.ss.reset_carry(ss));
-    }
+    RCCHK(g.ss.reset_carry(ss));
     std::vector<size_t> marks;
     marks.reserve(nblocks);
     if (g.tune.graph) {
@@ -851,12 +864,14 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
         const uint32_t slot = (uint32_t)(bi % slots);
         const BlockArgs b = g.ss.make_block(y1, y2, slot);
         marks.push_back(ev);
-        if (bi >= slots)
+        if (ahead && bi >= slots)
             HIPCHK(hipStreamWaitEvent(ss, g.updated_ev[slot], 0));
         RCCHK(g.ss.sieve(b, ss, g.events[ev]));
         HIPCHK(hipEventRecord(g.events[ev + 1], ss));
-        HIPCHK(hipEventRecord(g.sieved_ev[slot], ss));
-        HIPCHK(hipStreamWaitEvent(s, g.sieved_ev[slot], 0));
+        if (ahead) {
+            HIPCHK(hipEventRecord(g.sieved_ev[slot], ss));
+            HIPCHK(hipStreamWaitEvent(s, g.sieved_ev[slot], 0));
+        }
         HIPCHK(hipEventRecord(g.events[ev + 2], s));
         const uint64_t W = g.tune.update_window ? (1ull << g.tune.update_window) : 0;
         if (W && y1 < g.tune.window_ymax && y2 - y1 >= W &&
@@ -872,7 +887,8 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
             RCCHK(bt.update_block(b, grid, s, g.events[ev + 3]));
         }
         HIPCHK(hipEventRecord(g.events[ev + 4], s));
-        HIPCHK(hipEventRecord(g.updated_ev[slot], s));
+        if (ahead)
+            HIPCHK(hipEventRecord(g.updated_ev[slot], s));
         ev += 5;
     }
     HIPCHK(hipEventRecord(g.events[ev], s));
@@ -883,7 +899,8 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
     HIPCHK(hipMemcpyAsync(res.data(), bt.out_dev.p, nq * 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(pst, bt.pair_stats.p, 32, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipStreamSynchronize(ss));
+    if (ahead)
+        HIPCHK(hipStreamSynchronize(ss));
 
     // kernel times per stream; with sieve-ahead they overlap, so their sum
     // can exceed the total
