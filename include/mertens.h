@@ -137,8 +137,9 @@ int mertens_set_stream(void *hip_stream);
  *   "ychunk"      y per work item of the run-length part, multiple of 64
  *                 in [64, 2^20] (default 16384)
  *   "kchunk"      k per work item of the explicit k part (default 1024)
- *   "klchunk"     k per lane and work item where a tile's x have disjoint
- *                 k ranges (default 256)
+ *   "kbal"        explicit-k tiles whose 8 x 8 walk would keep fewer than
+ *                 1/kbal of its lanes busy take balanced per-lane runs of
+ *                 their pairs instead (default 0: never)
  *   "waves_per_cu" persistent update grid size per compute unit (default 16)
  *   "graph"       1: replay one captured hipGraph of the per-block kernel
  *                 sequence; 0: direct launches (default)

@@ -30,6 +30,9 @@ constexpr uint32_t SQ_BUCKET = 64;
 // pattern covers 5, 7, 11, 13, so sieving starts at 17 = index 4).
 constexpr uint32_t FIRST_SIEVED = 4;
 constexpr int TILE = 64;                     // x per tile = one wavefront
+// explicit-k pairs per balanced work item (tiles whose x have k ranges too
+// different for the 8 x 8 walk): 256 per lane
+constexpr uint64_t K_BAL_PAIRS = 64 * 256;
 constexpr int UPD_THREADS = 256;             // 4 independent waves per workgroup
 
 // ---------------------------------------------------------------- arguments
@@ -97,7 +100,8 @@ struct QueryArgs {
     uint64_t *pair_stats;               // [0] y-side visits, [1] k pairs
     // tuning
     double beta;
-    uint32_t ychunk, kchunk, klchunk;
+    uint32_t ychunk, kchunk;
+    uint32_t kbal;     // balanced runs where the 8 x 8 walk would use < 1/kbal of its lanes
     uint32_t rl_fast;  // 1: check-free fp64 floors where every m < 2^48
 };
 

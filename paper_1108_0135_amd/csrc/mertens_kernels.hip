@@ -680,18 +680,27 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockA
         atomicAdd((unsigned long long *)&q.pair_stats[3], (unsigned long long)kpairs);
     const uint64_t tmin = wave_min_u64(has ? klo : ~0ull);
     const uint64_t tmax = wave_max_u64(has ? khi : 0ull);
-    const uint64_t mlen = wave_max_u64(has ? khi - klo + 1 : 0ull);
+    // lane-slots the 8 x 8 walk would spend: each x-group of 8 lanes walks
+    // the union of its k ranges, 8 k at a time
+    uint64_t glo = has ? klo : ~0ull, ghi = has ? khi : 0ull;
+    for (int o = 1; o < 8; o <<= 1) {
+        const uint64_t a = __shfl_xor(glo, o, 64), c = __shfl_xor(ghi, o, 64);
+        glo = a < glo ? a : glo;
+        ghi = c > ghi ? c : ghi;
+    }
+    const uint64_t slots =
+        wave_sum_u64((lane & 7u) == 0 && glo <= ghi ? 8 * (ghi - glo + 1) : 0ull);
     if (lane == 0) {
         uint64_t nk = 0;
         uint32_t mode = 0;
-        if (mlen > 0) {
+        if (kpairs > 0) {
             const uint64_t uni = tmax - tmin + 1;
-            if (uni <= 4 * mlen) {
-                mode = 0;
+            if (q.kbal == 0 || q.kbal * kpairs >= slots) {
+                mode = 0;  // the 8 x 8 walk keeps at least 1/kbal of its lanes busy
                 nk = (uni + q.kchunk - 1) / q.kchunk;
             } else {
-                mode = 1;
-                nk = (mlen + q.klchunk - 1) / q.klchunk;
+                mode = 1;  // balanced runs of the tile's pairs
+                nk = (kpairs + K_BAL_PAIRS - 1) / K_BAL_PAIRS;
             }
         }
         q.tile_klo[tile] = tmin;
@@ -1215,10 +1224,10 @@ __device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_
         atomicAdd((unsigned long long *)&q.S[g0 + xo], (unsigned long long)mine);
 }
 
-// Explicit k part of one (tile, k-chunk) item: S[x] += M(floor(m_x / k)) for
-// k in the chunk and in x's range [klo, khi] of this block.  Mode 0 tiles
-// (k ranges of the tile's x overlap) use the 8 x 8 grid above; mode 1 tiles
-// (disjoint ranges) let each lane walk its own x's range in klchunk steps.
+// Explicit k part of one (tile, chunk) item: S[x] += M(floor(m_x / k)) for
+// k in x's range [klo, khi] of this block.  Mode 0 tiles (k ranges of
+// neighbouring x alike) use the 8 x 8 grid above over k-chunks; mode 1
+// tiles use balanced runs of their pairs.
 __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t tile, uint64_t c,
                               double *rk)
 {
@@ -1226,34 +1235,73 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
         k_item_2d(q, b, tile, c, rk);
         return;
     }
+    // Balanced runs: the tile's pairs are numbered through an exclusive
+    // prefix over its x; item c takes pairs [c K_BAL_PAIRS, ...) and splits
+    // them into 64 equal contiguous runs, one per lane.  A lane walks its
+    // run's k (one x at a time, K_UNROLL gathers in flight) and adds each x's
+    // sum with one atomic.
     const uint32_t lane = lane_id();
-    const uint32_t nx = q.tile_nx[tile];
-    const uint64_t g = q.tile_g0[tile] + lane;
-    const bool valid = lane < nx;
-    const uint64_t m = valid ? q.x_m[g] : 0;
-    const uint64_t klo = valid ? q.x_klo[g] : 1;
-    const uint64_t khi = valid ? q.x_khi[g] : 0;
-    uint64_t acc = 0;
-    const uint64_t ks = klo + c * q.klchunk;
-    uint64_t ke = ks + q.klchunk - 1;
-    if (ke > khi)
-        ke = khi;
-    const double mf = (double)m;
-    for (uint64_t k0 = ks; k0 <= ke && klo <= khi; k0 += K_UNROLL) {
-        uint64_t off[K_UNROLL];
-        bool act[K_UNROLL];
-#pragma unroll
-        for (int u = 0; u < K_UNROLL; ++u) {
-            const uint64_t k = k0 + u;
-            act[u] = k <= ke;
-            off[u] = 0;
-            if (act[u])
-                off[u] = fix_quotient_any(m, k, trunc(mf / (double)k)) - b.y1;
-        }
-        acc += M_sum_masked(b.words, off, act);
+    const uint32_t nx = __builtin_amdgcn_readfirstlane(q.tile_nx[tile]);
+    const uint64_t g0 = uniform_u64(q.tile_g0[tile]);
+    uint64_t m = 0, klo = 1, cnt = 0;
+    if (lane < nx) {
+        m = q.x_m[g0 + lane];
+        klo = q.x_klo[g0 + lane];
+        const uint64_t khi = q.x_khi[g0 + lane];
+        cnt = klo <= khi ? khi - klo + 1 : 0;
     }
-    if (valid)
-        atomicAdd((unsigned long long *)&q.S[g], (unsigned long long)acc);
+    uint64_t incl = cnt;
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t t = __shfl_up(incl, o, 64);
+        if (lane >= (uint32_t)o)
+            incl += t;
+    }
+    const uint64_t T = readlane_u64(incl, 63);
+    const uint64_t pa = c * K_BAL_PAIRS;
+    const uint64_t pb = (T - pa) < K_BAL_PAIRS ? T : pa + K_BAL_PAIRS;
+    uint64_t *sm = reinterpret_cast<uint64_t *>(rk);  // m, first k, prefix per x
+    uint64_t *sk = sm + 64, *se = sm + 128;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    sm[lane] = m;
+    sk[lane] = klo;
+    se[lane] = incl - cnt;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    uint64_t p = pa + (pb - pa) * lane / 64;
+    const uint64_t p1 = pa + (pb - pa) * (lane + 1) / 64;
+    if (p >= p1)
+        return;
+    // x of pair p: the last x whose prefix is <= p (it has pairs left)
+    uint32_t e = 0;
+    for (uint32_t step = 32; step >= 1; step >>= 1)
+        if (e + step < 64 && se[e + step] <= p)
+            e += step;
+    while (p < p1) {
+        const uint64_t me = sm[e];
+        const uint64_t pend = e < 63 ? se[e + 1] : T;  // first pair of the next x
+        const uint64_t stop = pend < p1 ? pend : p1;
+        const uint64_t kend = sk[e] + (stop - se[e]);  // exclusive
+        const double mf = (double)me;
+        uint64_t acc = 0;
+        for (uint64_t k = sk[e] + (p - se[e]); k < kend; k += K_UNROLL) {
+            uint64_t off[K_UNROLL];
+            bool act[K_UNROLL];
+#pragma unroll
+            for (int u = 0; u < K_UNROLL; ++u) {
+                const uint64_t kk = k + u;
+                act[u] = kk < kend;
+                off[u] = 0;
+                if (act[u])
+                    off[u] = fix_quotient_any(me, kk, trunc(mf / (double)kk)) - b.y1;
+            }
+            acc += M_sum_masked(b.words, off, act);
+        }
+        atomicAdd((unsigned long long *)&q.S[g0 + e], (unsigned long long)acc);
+        p = stop;
+        while (p < p1 && e < 63 && se[e + 1] <= p)  // next x with pairs
+            ++e;
+    }
 }
 
 // Persistent update kernel of one block: wave w starts on item w and then

@@ -162,7 +162,8 @@ uint64_t auto_u(long double total_n, double scale)
 struct Tuning {
     double u_scale = 0.5;  // automatic u = u_scale * (clustered sum of the batch's n)^(2/3)
     double beta = 0.25;
-    uint32_t ychunk = 16384, kchunk = 1024, klchunk = 256, waves_per_cu = 16;
+    uint32_t ychunk = 16384, kchunk = 1024, waves_per_cu = 16;
+    uint32_t kbal = 0;  // 0: every tile takes the 8 x 8 walk (measured best at 1e16)
     uint32_t sieve_ahead = 4;  // most record slots (blocks sieved ahead of the update)
     // blocks starting below window_ymax are updated in windows of
     // 2^update_window y, so the records that the explicit-k gathers of one
@@ -590,8 +591,8 @@ struct Batch {
         q.beta = t.beta;
         q.ychunk = t.ychunk;
         q.kchunk = t.kchunk;
-        q.klchunk = t.klchunk;
         q.rl_fast = t.rl_fast;
+        q.kbal = t.kbal;
         HIPCHK(launch_zero_u64(pair_stats.as<uint64_t>(), 4, s));
         HIPCHK(launch_plan(q, s));
         return 0;
@@ -1344,6 +1345,10 @@ int mertens_set_param(const char *key, double value)
         if (!(value >= 64 && value <= (1 << 24)))
             return MERTENS_EINVAL;
         g.tune.kchunk = (uint32_t)value;
+    } else if (!strcmp(key, "kbal")) {
+        if (!(value >= 0 && value <= 1024) || value != (double)(int)value)
+            return MERTENS_EINVAL;
+        g.tune.kbal = (uint32_t)value;
     } else if (!strcmp(key, "rl_fast")) {
         if (!(value == 0.0 || value == 1.0))
             return MERTENS_EINVAL;
@@ -1356,10 +1361,6 @@ int mertens_set_param(const char *key, double value)
         if (!(value >= 1 && value <= 256))
             return MERTENS_EINVAL;
         g.tune.sieve_ahead = (uint32_t)value;
-    } else if (!strcmp(key, "klchunk")) {
-        if (!(value >= 1 && value <= (1 << 24)))
-            return MERTENS_EINVAL;
-        g.tune.klchunk = (uint32_t)value;
     } else if (!strcmp(key, "waves_per_cu")) {
         if (!(value >= 4 && value <= 64))
             return MERTENS_EINVAL;

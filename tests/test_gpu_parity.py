@@ -110,11 +110,13 @@ def test_n1e12_and_byproducts(mt):
     (10**8, 1 << 17, {}),
     (3 * 10**7, 1 << 20, {"beta": 1.0}),
     (2 * 10**8, 1 << 24, {"beta": 0.25, "ychunk": 64, "kchunk": 64}),
-    (10**8, 1 << 26, {"ychunk": 1 << 16, "kchunk": 1 << 15, "klchunk": 1}),
+    (10**8, 1 << 26, {"ychunk": 1 << 16, "kchunk": 1 << 15}),
     # update windows of 2^18 y inside 2^24-y blocks; sieve strictly in turn
     (10**8, 1 << 24, {"update_window": 18, "sieve_ahead": 1}),
     # the tested run-length path everywhere; many record slots
     (10**8, 1 << 20, {"rl_fast": 0, "sieve_ahead": 64}),
+    # balanced explicit-k runs for every tile the 8 x 8 walk would use badly
+    (10**8, 1 << 26, {"kbal": 64}),
 ])
 def test_n1e12_invariance(mt, u, block, params):
     g = GOLDEN["n1e12"]
