@@ -154,6 +154,9 @@ int mertens_set_stream(void *hip_stream);
  *                 test-free rounded-up fp64 floor; 0: always the tested path
  *   "serve_capacity"  most requests in flight for mertens_submit (4096)
  *   "serve_x_budget"  most x entries of admitted requests (2^26 = 4 GiB)
+ *   "serve_short_blocks" requests whose sweep ends within this many blocks
+ *                 ride a separate short sweep, stepped alternately with the
+ *                 main one (default 4)
  * Returns 0 or MERTENS_EINVAL (unknown key, value out of range, or a
  * non-serving key while the serving worker runs).
  */

@@ -661,6 +661,13 @@ struct ServeBatch {
     uint64_t x_entries = 0;
 };
 
+// One cyclic sweep of the serving worker with the batches riding on it.
+struct ServeLane {
+    SieveState ss;
+    std::vector<std::unique_ptr<ServeBatch>> batches;  // worker thread only
+    uint64_t cur_block = 0;
+};
+
 struct Server {
     std::thread worker;
     std::mutex mu;
@@ -668,13 +675,15 @@ struct Server {
     bool running = false, stop = false;
     int failure = 0;
     hipStream_t stream = nullptr;
-    SieveState ss;
+    // lane 0 sweeps the first serve_short_blocks blocks for requests that
+    // need no more; lane 1 sweeps for the rest.  Each worker step runs one
+    // block of each busy lane, so short requests never wait for the sweep
+    // of long ones.
+    ServeLane lanes[2];
     std::deque<uint64_t> queued;
     std::map<uint64_t, ServeQuery> queries;
-    std::vector<std::unique_ptr<ServeBatch>> batches;  // worker thread only
     uint64_t next_ticket = 1;
     uint64_t x_used = 0;
-    uint64_t cur_block = 0;
     uint64_t blocks_run = 0;
 };
 
@@ -690,6 +699,7 @@ struct Ctx {
     Tuning tune;
     size_t serve_capacity = 4096;
     uint64_t serve_x_budget = 1ull << 26;  // x entries in flight (64 B each)
+    uint64_t serve_short_blocks = 4;       // requests needing at most this many blocks
     SieveState ss;
     Batch batch;
     // last query (for byproducts): per caller index, L and first global index
@@ -944,67 +954,76 @@ void serve_fail(int rc)
     v.queued.clear();
 }
 
-// One worker step: admit queued requests as a new batch, run one block of
-// the cyclic sweep for every batch in it, finalize finished queries.
-int serve_step(std::vector<uint64_t> &admit)
+// Plan the admitted tickets as one batch and put it on the lane its
+// longest request needs.
+int serve_admit(const std::vector<uint64_t> &tickets, uint64_t B)
 {
     Server &v = g.srv;
     hipStream_t s = v.stream;
-    const uint64_t B = g.block_req ? g.block_req : (1ull << 30);
-    if (!admit.empty()) {
-        auto sb = std::make_unique<ServeBatch>();
-        std::vector<uint64_t> ns, us;
-        {
-            std::lock_guard<std::mutex> lk(v.mu);
-            for (uint64_t t : admit)
-                ns.push_back(v.queries[t].n);
-        }
-        for (uint64_t x : ns)
-            us.push_back(g.u_req ? g.u_req : auto_u((long double)x, g.tune.u_scale));
-        // no keyed groups here: requests complete and finalize one by one
-        RCCHK(sb->b.plan(ns, us, g.tune, s, false));
-        sb->tickets = admit;
-        sb->open = admit.size();
-        sb->x_entries = sb->b.X;
+    auto sb = std::make_unique<ServeBatch>();
+    std::vector<uint64_t> ns, us;
+    {
         std::lock_guard<std::mutex> lk(v.mu);
-        for (size_t i = 0; i < admit.size(); ++i) {
-            ServeQuery &q = v.queries[admit[i]];
+        for (uint64_t t : tickets)
+            ns.push_back(v.queries[t].n);
+    }
+    for (uint64_t x : ns)
+        us.push_back(g.u_req ? g.u_req : auto_u((long double)x, g.tune.u_scale));
+    // no keyed groups here: requests complete and finalize one by one
+    RCCHK(sb->b.plan(ns, us, g.tune, s, false));
+    sb->tickets = tickets;
+    sb->open = tickets.size();
+    sb->x_entries = sb->b.X;
+    uint64_t maxlb = 0;
+    {
+        std::lock_guard<std::mutex> lk(v.mu);
+        for (size_t i = 0; i < tickets.size(); ++i) {
+            ServeQuery &q = v.queries[tickets[i]];
             q.state = 1;
             q.idx = (uint32_t)i;
             q.last_block = sb->b.ymax[i] / B;
             q.seen = 0;
             q.seen_map.assign(q.last_block + 1, 0);
+            maxlb = std::max(maxlb, q.last_block);
         }
-        v.batches.push_back(std::move(sb));
     }
-    if (v.batches.empty())
-        return 0;
+    v.lanes[maxlb < g.serve_short_blocks ? 0 : 1].batches.push_back(std::move(sb));
+    return 0;
+}
 
-    // pass length: every block some query in flight still needs
+// One block of lane ln's cyclic sweep for every batch on it; finalize the
+// queries that have now seen every block they need.
+int serve_lane_step(ServeLane &ln, uint64_t B)
+{
+    Server &v = g.srv;
+    hipStream_t s = v.stream;
+    if (ln.batches.empty())
+        return 0;
+    // pass length: every block some query in flight on the lane still needs
     uint64_t ymax = 0;
     {
         std::lock_guard<std::mutex> lk(v.mu);
-        for (auto &sb : v.batches)
+        for (auto &sb : ln.batches)
             for (size_t i = 0; i < sb->tickets.size(); ++i)
                 if (v.queries[sb->tickets[i]].state == 1)
                     ymax = std::max(ymax, sb->b.ymax[i]);
     }
     const uint64_t nb = ymax / B + 1;
-    if (v.cur_block >= nb)
-        v.cur_block = 0;
+    if (ln.cur_block >= nb)
+        ln.cur_block = 0;
     // Blocks are always sieved whole: the pass may grow while it runs, and
     // the carry into the next block must then cover the whole block.
-    RCCHK(v.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(nb * B), 1024)));
-    RCCHK(v.ss.ensure_pattern());
-    RCCHK(v.ss.ensure_blocks(B));
-    if (v.cur_block == 0)
-        RCCHK(v.ss.reset_carry(s));
-    const uint64_t y1 = v.cur_block * B;
+    RCCHK(ln.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(nb * B), 1024)));
+    RCCHK(ln.ss.ensure_pattern());
+    RCCHK(ln.ss.ensure_blocks(B));
+    if (ln.cur_block == 0)
+        RCCHK(ln.ss.reset_carry(s));
+    const uint64_t y1 = ln.cur_block * B;
     const uint64_t y2 = y1 + B - 1;
-    const BlockArgs b = v.ss.make_block(y1, y2);
-    RCCHK(v.ss.sieve(b, s, nullptr));
+    const BlockArgs b = ln.ss.make_block(y1, y2);
+    RCCHK(ln.ss.sieve(b, s, nullptr));
     const uint32_t grid = update_grid(g.ncu, g.tune);
-    for (auto &sb : v.batches)
+    for (auto &sb : ln.batches)
         if (sb->open)
             RCCHK(sb->b.update_block(b, grid, s, nullptr));
 
@@ -1012,14 +1031,14 @@ int serve_step(std::vector<uint64_t> &admit)
     std::vector<std::pair<ServeBatch *, std::vector<uint32_t>>> done;
     {
         std::lock_guard<std::mutex> lk(v.mu);
-        for (auto &sb : v.batches) {
+        for (auto &sb : ln.batches) {
             std::vector<uint32_t> fin;
             for (size_t i = 0; i < sb->tickets.size(); ++i) {
                 ServeQuery &q = v.queries[sb->tickets[i]];
                 if (q.state != 1)
                     continue;
-                if (v.cur_block <= q.last_block && !q.seen_map[v.cur_block]) {
-                    q.seen_map[v.cur_block] = 1;
+                if (ln.cur_block <= q.last_block && !q.seen_map[ln.cur_block]) {
+                    q.seen_map[ln.cur_block] = 1;
                     q.seen++;
                 }
                 if (q.seen == q.last_block + 1)
@@ -1029,7 +1048,7 @@ int serve_step(std::vector<uint64_t> &admit)
                 done.emplace_back(sb.get(), fin);
         }
     }
-    v.cur_block++;
+    ln.cur_block++;
     v.blocks_run++;
     for (auto &d : done) {
         ServeBatch *sb = d.first;
@@ -1050,16 +1069,43 @@ int serve_step(std::vector<uint64_t> &admit)
     // retire batches whose queries are all finalized
     {
         std::lock_guard<std::mutex> lk(v.mu);
-        for (auto it = v.batches.begin(); it != v.batches.end();) {
+        for (auto it = ln.batches.begin(); it != ln.batches.end();) {
             if ((*it)->open == 0) {
                 v.x_used -= (*it)->x_entries;
                 (*it)->b.release();
-                it = v.batches.erase(it);
+                it = ln.batches.erase(it);
             } else {
                 ++it;
             }
         }
     }
+    return 0;
+}
+
+// One worker step: admit queued requests (split by lane), then one block of
+// each busy lane.
+int serve_step(std::vector<uint64_t> &admit)
+{
+    Server &v = g.srv;
+    const uint64_t B = g.block_req ? g.block_req : (1ull << 30);
+    if (!admit.empty()) {
+        std::vector<uint64_t> by_lane[2];
+        for (uint64_t t : admit) {
+            uint64_t n;
+            {
+                std::lock_guard<std::mutex> lk(v.mu);
+                n = v.queries[t].n;
+            }
+            const uint64_t u = g.u_req ? g.u_req : auto_u((long double)n, g.tune.u_scale);
+            const uint64_t L = std::max<uint64_t>(1, n / u);
+            by_lane[(n / (L + 1)) / B < g.serve_short_blocks ? 0 : 1].push_back(t);
+        }
+        for (auto &tl : by_lane)
+            if (!tl.empty())
+                RCCHK(serve_admit(tl, B));
+    }
+    for (ServeLane &ln : v.lanes)
+        RCCHK(serve_lane_step(ln, B));
     v.cv.notify_all();
     return 0;
 }
@@ -1075,7 +1121,10 @@ void serve_loop()
         std::vector<uint64_t> admit;
         {
             std::unique_lock<std::mutex> lk(v.mu);
-            v.cv.wait(lk, [&] { return v.stop || !v.queued.empty() || !v.batches.empty(); });
+            v.cv.wait(lk, [&] {
+                return v.stop || !v.queued.empty() || !v.lanes[0].batches.empty() ||
+                       !v.lanes[1].batches.empty();
+            });
             if (v.stop)
                 break;
             // admission by device memory: x entries in flight stay within budget
@@ -1100,9 +1149,11 @@ void serve_loop()
         }
     }
     std::lock_guard<std::mutex> lk(v.mu);
-    for (auto &sb : v.batches)
-        sb->b.release();
-    v.batches.clear();
+    for (ServeLane &ln : v.lanes) {
+        for (auto &sb : ln.batches)
+            sb->b.release();
+        ln.batches.clear();
+    }
 }
 
 int serve_start()
@@ -1113,7 +1164,8 @@ int serve_start()
     HIPCHK(hipStreamCreateWithFlags(&v.stream, hipStreamNonBlocking));
     v.stop = false;
     v.failure = 0;
-    v.cur_block = 0;
+    for (ServeLane &ln : v.lanes)
+        ln.cur_block = 0;
     v.x_used = 0;
     v.running = true;
     v.worker = std::thread(serve_loop);
@@ -1134,7 +1186,8 @@ void serve_stop()
     (void)hipStreamSynchronize(v.stream);
     (void)hipStreamDestroy(v.stream);
     v.stream = nullptr;
-    v.ss.release();
+    for (ServeLane &ln : v.lanes)
+        ln.ss.release();
     v.queries.clear();
     v.queued.clear();
     v.running = false;
@@ -1370,6 +1423,11 @@ int mertens_set_param(const char *key, double value)
             return MERTENS_EINVAL;
         std::lock_guard<std::mutex> lk(g.srv.mu);
         g.serve_capacity = (size_t)value;
+    } else if (!strcmp(key, "serve_short_blocks")) {
+        if (!(value >= 0 && value <= 1e9))
+            return MERTENS_EINVAL;
+        std::lock_guard<std::mutex> lk(g.srv.mu);
+        g.serve_short_blocks = (uint64_t)value;
     } else if (!strcmp(key, "serve_x_budget")) {
         if (!(value >= 1 && value <= 1e12))
             return MERTENS_EINVAL;

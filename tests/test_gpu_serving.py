@@ -12,6 +12,8 @@ import time
 
 import pytest
 
+from paper_1108_0135_amd import inputs
+
 pytestmark = pytest.mark.gpu
 
 GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "golden.json")))
@@ -77,3 +79,16 @@ def test_capacity_and_zero(mt):
     assert _collect(mt, [z])[z] == (0, 0.0)
     with pytest.raises(Exception):
         mt.poll(z)  # already collected
+
+
+def test_short_request_overtakes_long_sweep(mt):
+    # a long request keeps the main sweep busy for thousands of 2^24-y blocks;
+    # a short one rides the short sweep and finishes first, with its exact value
+    long_t = mt.submit(10**17)
+    time.sleep(0.1)
+    short_n = GOLDEN["seeded32"]["n"][0]
+    short_t = mt.submit(short_n)
+    got = _collect(mt, [short_t])
+    assert got[short_t][0] == GOLDEN["seeded32"]["M"][0]
+    assert mt.poll(long_t) is None  # still sweeping
+    assert _collect(mt, [long_t], timeout=300)[long_t][0] == inputs.TABLE1[10**17]
