@@ -215,6 +215,13 @@ def test_window_keyed_small_vs_oracle(mt):
         assert np.array_equal(byp, ref)
 
 
+def test_window_keyed_graph_replay(mt):
+    # keyed groups through the captured block pipeline
+    _reinit(mt, u=10**7, block=1 << 24, graph=1)
+    ns = inputs.dense_window(seed=4, count=32, lo=5 * 10**8, hi=10**9 - 32 * 997)
+    assert np.array_equal(mt.query(ns), oracle.mertens_many(ns))
+
+
 def test_window1e12_golden(mt):
     _reinit(mt)
     g = GOLDEN["window1e12"]
@@ -251,3 +258,17 @@ def test_window1e19_full_size_differences(mt):
     got = [int(v) for v in mt.query(ns)]
     assert [got[i + 1] - got[i] for i in range(7)] == g["diffs"]
     assert int(mt.query([ns[0]])[0]) == got[0]
+
+
+def test_batched_256_full_size_sampled(mt):
+    # the batched workload at its real size (256 n log-uniform in [1e13, 1e17],
+    # seed 0, plus 1e16 and 1e17) in one shared sweep; Table 1 pins two
+    # members, and sampled members must equal the plain one-at-a-time path
+    _reinit(mt)
+    ns = [int(v) for v in inputs.batch_log_uniform(seed=0, count=256, lo=1e13, hi=1e17)]
+    ns += [10**16, 10**17]
+    got = [int(v) for v in mt.query(ns)]
+    assert got[-2] == inputs.TABLE1[10**16] and got[-1] == inputs.TABLE1[10**17]
+    rng = np.random.default_rng(7)
+    for i in sorted(rng.choice(256, 12, replace=False)):
+        assert int(mt.query([ns[i]])[0]) == got[i], (i, ns[i])
