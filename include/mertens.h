@@ -150,6 +150,9 @@ int mertens_set_stream(void *hip_stream);
  *                 2^update_window y so that the random M(y) reads of one
  *                 window stay cache-resident (17..40; default 0: whole
  *                 blocks)
+ *   "bucket_min"  a block sieving at least this many primes above 2^17
+ *                 lists their multiples in per-segment buckets first
+ *                 (default 2^20; scanning them per segment is faster below)
  *   "rl_fast"     1 (default): run-length quotients with m < 2^48 take the
  *                 test-free rounded-up fp64 floor; 0: always the tested path
  *   "serve_capacity"  most requests in flight for mertens_submit (4096)

@@ -26,6 +26,12 @@ constexpr uint32_t SMALL_P = SEG / 64;
 // SQ_BUCKET entries (a segment whose bucket overflows scans every prime).
 constexpr uint32_t SQ_LDS_P = 1024;
 constexpr uint32_t SQ_BUCKET = 64;
+// Primes above SEG meet a segment at most once; when a block has many of
+// them, BK_WGS workgroups (each a fixed share of those primes) list their
+// multiples into per-segment buckets in two passes (count, fill), so the
+// sieve reads its hits instead of testing every such prime.
+constexpr uint32_t BK_WGS = 512, BK_THREADS = 1024;
+constexpr uint32_t MAX_SEGS = (1u << 31) / SEG;  // segments of the longest block
 // First index of the prime table that is sieved (table starts at 5; the
 // pattern covers 5, 7, 11, 13, so sieving starts at 17 = index 4).
 constexpr uint32_t FIRST_SIEVED = 4;
@@ -42,7 +48,8 @@ constexpr int UPD_THREADS = 256;             // 4 independent waves per workgrou
 struct BlockParams {
     uint64_t y1, y2;
     uint32_t nseg, n_sq, n_sq_lds, pat_off;
-    uint32_t n_sieve, pad;
+    uint32_t n_sieve;
+    uint32_t n_bucket;  // primes with index in [n_bucket, n_sieve) reach the sieve through buckets
 };
 
 // One y-block [y1, y2] of the sweep.  The scalar fields below mirror *bp on
@@ -55,6 +62,7 @@ struct BlockArgs {
     uint32_t n_sieve;   // primes with index < n_sieve are sieved (p <= max(sqrt(y2), SMALL_P))
     uint32_t n_sq_lds;  // primes with index < n_sq_lds have p <= SQ_LDS_P
     uint32_t n_sq;      // primes with index < n_sq have p^2 <= y2
+    uint32_t n_bucket;  // primes with index in [n_bucket, n_sieve) (all > SEG) are bucketed
     uint32_t pat_off;   // y1 mod PAT
     uint2 *pres;              // {p, y1 mod p}: primes >= 5 ascending, residue per block
     uint64_t *res2;           // y1 mod p^2    (per block)
@@ -68,6 +76,11 @@ struct BlockArgs {
     uint32_t *seg_ticket;     // segments are claimed in ticket order
     uint32_t *sq_cnt;         // per segment: large-square hits listed (may exceed SQ_BUCKET)
     uint32_t *sq_buf;         // per segment: SQ_BUCKET offsets of large-square multiples
+    // bucketed primes: per (bucket workgroup, segment) counts, then offsets;
+    // per segment first entry (nseg + 1); entries (offset in segment | log << 17)
+    uint32_t *bk_cnt;
+    uint32_t *bk_start;
+    uint32_t *bk_buf;
     int64_t *carry;           // M(y1 - 1), advanced by the block's last segment
 };
 
@@ -116,6 +129,8 @@ hipError_t launch_block_next(const BlockParams *table, BlockParams *cur, uint32_
 hipError_t launch_plan(const QueryArgs &q, hipStream_t s);
 hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s);
 hipError_t launch_square_buckets(const BlockArgs &b, hipStream_t s);
+// multiples of the primes above SEG, sorted into per-segment buckets
+hipError_t launch_prime_buckets(const BlockArgs &b, hipStream_t s);
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s);
 hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
 hipError_t launch_scan_items(const QueryArgs &q, hipStream_t s);

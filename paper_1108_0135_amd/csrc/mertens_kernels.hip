@@ -210,6 +210,7 @@ __device__ inline BlockArgs load_block(BlockArgs b)
     b.n_sq_lds = p.n_sq_lds;
     b.pat_off = p.pat_off;
     b.n_sieve = p.n_sieve;
+    b.n_bucket = p.n_bucket;
     return b;
 }
 
@@ -380,6 +381,105 @@ hipError_t launch_square_buckets(const BlockArgs &b, hipStream_t s)
     return hipGetLastError();
 }
 
+// Bucketed primes p > SEG (index in [n_bucket, n_sieve)): wave v of
+// workgroup w takes the primes n_bucket + w * 16 + v + j * BK_WGS * 16, its
+// lanes the multiples lane, lane + 64, ... (at most B / p <= 2^14 of them).
+// Pass 1 counts the workgroup's hits per segment in LDS and stores the
+// counts; k_bucket_columns / k_bucket_starts turn them into each
+// workgroup's first entry per segment; pass 2 writes the entries there.
+__device__ inline uint32_t bucket_entry(uint64_t o, uint32_t lp)
+{
+    return (uint32_t)(o % SEG) | (lp << 17);
+}
+
+template <bool FILL>
+__global__ __launch_bounds__(BK_THREADS) void k_prime_buckets(BlockArgs b_in)
+{
+    const BlockArgs b = load_block(b_in);
+    __shared__ uint32_t cnt[MAX_SEGS];
+    if (b.n_bucket >= b.n_sieve)
+        return;
+    const uint32_t tid = threadIdx.x, w = blockIdx.x;
+    uint32_t *mine = b.bk_cnt + (size_t)w * b.nseg;
+    for (uint32_t sg = tid; sg < b.nseg; sg += BK_THREADS)
+        cnt[sg] = FILL ? b.bk_start[sg] + mine[sg] : 0u;
+    __syncthreads();
+    const uint64_t span = (uint64_t)b.nseg * SEG;
+    constexpr uint32_t WAVES = BK_THREADS / 64;
+    const uint32_t lane = lane_id();
+    const uint32_t v = __builtin_amdgcn_readfirstlane(tid >> 6);
+    for (uint64_t i = b.n_bucket + (uint64_t)w * WAVES + v; i < b.n_sieve;
+         i += (uint64_t)BK_WGS * WAVES) {
+        const uint2 e = b.pres[i];
+        const uint64_t p = e.x;
+        const uint32_t lp = log_prime(e.x);
+        for (uint64_t o = (e.y ? p - e.y : 0) + lane * p; o < span; o += 64 * p) {
+            if (FILL) {
+                const uint32_t k = atomicAdd(&cnt[o / SEG], 1u);
+                b.bk_buf[k] = bucket_entry(o, lp);
+            } else {
+                atomicAdd(&cnt[o / SEG], 1u);
+            }
+        }
+    }
+    __syncthreads();
+    if (!FILL)
+        for (uint32_t sg = tid; sg < b.nseg; sg += BK_THREADS)
+            mine[sg] = cnt[sg];
+}
+
+// Per segment (one thread each): exclusive prefix of the workgroups' counts
+// (in place) and the segment's total, into bk_start.
+__global__ void k_bucket_columns(BlockArgs b_in)
+{
+    const BlockArgs b = load_block(b_in);
+    const uint32_t sg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b.n_bucket >= b.n_sieve || sg >= b.nseg)
+        return;
+    uint32_t tot = 0;
+    for (uint32_t w = 0; w < BK_WGS; ++w) {
+        uint32_t *c = b.bk_cnt + (size_t)w * b.nseg + sg;
+        const uint32_t v = *c;
+        *c = tot;
+        tot += v;
+    }
+    b.bk_start[sg] = tot;
+}
+
+// Segment totals -> each segment's first entry (exclusive prefix), and the
+// total at [nseg].
+__global__ __launch_bounds__(SIEVE_THREADS) void k_bucket_starts(BlockArgs b_in)
+{
+    const BlockArgs b = load_block(b_in);
+    __shared__ int64_t wsum[SIEVE_THREADS / 64];
+    if (b.n_bucket >= b.n_sieve)
+        return;
+    const uint32_t tid = threadIdx.x;
+    uint64_t base = 0;
+    for (uint32_t s0 = 0; s0 < b.nseg; s0 += SIEVE_THREADS) {
+        const uint32_t sg = s0 + tid;
+        const uint32_t tot = sg < b.nseg ? b.bk_start[sg] : 0u;
+        int64_t all;
+        const int64_t ex = wg_exclusive_scan<SIEVE_THREADS>((int64_t)tot, wsum, all);
+        if (sg < b.nseg)
+            b.bk_start[sg] = (uint32_t)(base + (uint64_t)ex);
+        base += (uint64_t)all;
+    }
+    if (tid == 0)
+        b.bk_start[b.nseg] = (uint32_t)base;
+}
+
+hipError_t launch_prime_buckets(const BlockArgs &b, hipStream_t s)
+{
+    if (b.n_bucket >= b.n_sieve)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_prime_buckets<false>, dim3(BK_WGS), dim3(BK_THREADS), 0, s, b);
+    hipLaunchKernelGGL(k_bucket_columns, dim3((b.nseg + 255) / 256), dim3(256), 0, s, b);
+    hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(SIEVE_THREADS), 0, s, b);
+    hipLaunchKernelGGL(k_prime_buckets<true>, dim3(BK_WGS), dim3(BK_THREADS), 0, s, b);
+    return hipGetLastError();
+}
+
 // Look-back states of the fused scan.
 constexpr uint64_t SEG_AGG = 1ull << 62, SEG_INCL = 2ull << 62;
 constexpr uint64_t SEG_VAL = (1ull << 62) - 1;
@@ -490,12 +590,13 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
     // larger primes (at most SEG/SMALL_P = 64 multiples): one lane per prime,
     // four primes' table entries loaded ahead of their walks
     const uint32_t i0 = (b.n_small > FIRST_SIEVED ? b.n_small : FIRST_SIEVED) + tid;
-    for (uint32_t i = i0; i < b.n_sieve; i += 4 * SIEVE_THREADS) {
+    const uint32_t i_end = b.n_bucket < b.n_sieve ? b.n_bucket : b.n_sieve;
+    for (uint32_t i = i0; i < i_end; i += 4 * SIEVE_THREADS) {
         uint2 e[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint32_t k = i + (uint32_t)u * SIEVE_THREADS;
-            e[u] = k < b.n_sieve ? b.pres[k] : make_uint2(0u, 0u);
+            e[u] = k < i_end ? b.pres[k] : make_uint2(0u, 0u);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -509,6 +610,15 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
             const uint64_t first = r ? p - r : 0;
             for (uint64_t o = first; o < SEG; o += p)
                 atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
+        }
+    }
+    // bucketed primes (> SEG): their hits in this segment, listed per block
+    if (b.n_bucket < b.n_sieve) {
+        const uint32_t e1 = b.bk_start[seg + 1];
+        for (uint32_t k = b.bk_start[seg] + tid; k < e1; k += SIEVE_THREADS) {
+            const uint32_t v = b.bk_buf[k];
+            const uint32_t o = v & (SEG - 1);
+            atomicAdd(&lds[o >> 2], (v >> 17) << ((o & 3u) << 3));
         }
     }
     // squares p^2 > SQ_LDS_P^2 (> SEG): at most one multiple each in the

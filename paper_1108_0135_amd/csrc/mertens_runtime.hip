@@ -180,14 +180,17 @@ struct Tuning {
 struct SieveState {
     uint64_t psieve = 0;
     std::vector<uint32_t> h_primes;  // primes >= 5 up to psieve
-    DevBuf pres, res2, pattern, words, seg_state, sq_cnt, sq_buf, carry, bp_cur, bp_table,
-        bp_index;
+    DevBuf pres, res2, pattern, words, seg_state, sq_cnt, sq_buf, bk_cnt, bk_start, bk_buf,
+        carry, bp_cur, bp_table, bp_index;
+    uint32_t bucket_min = 1u << 20;  // bucket the primes above SEG when a block has this many
+    long double bk_cap = 0;           // bucket entries a block of bk_cap_B can need
+    uint64_t bk_cap_B = 0, bk_cap_np = 0;
     bool have_pattern = false;
 
     void release()
     {
-        DevBuf *bufs[] = {&pres, &res2, &pattern, &words, &seg_state, &sq_cnt, &sq_buf, &carry,
-                          &bp_cur, &bp_table, &bp_index};
+        DevBuf *bufs[] = {&pres, &res2, &pattern, &words, &seg_state, &sq_cnt, &sq_buf,
+                          &bk_cnt, &bk_start, &bk_buf, &carry, &bp_cur, &bp_table, &bp_index};
         for (DevBuf *b : bufs)
             b->release();
         h_primes.clear();
@@ -265,6 +268,27 @@ struct SieveState {
         RCCHK(ensure(seg_state, B / SEG * 8));
         RCCHK(ensure(sq_cnt, B / SEG * 4));
         RCCHK(ensure(sq_buf, B / SEG * SQ_BUCKET * 4));
+        // bucketed primes: counts, starts, and every multiple in a block of
+        // any prime above SEG (at most B / p + 1 each)
+        const uint32_t n_mid = count_primes_upto(SEG);
+        if (h_primes.size() - n_mid >= bucket_min) {
+            if (bk_cap_B != B || bk_cap_np != h_primes.size()) {
+                long double c = 0;
+                for (size_t i = n_mid; i < h_primes.size(); ++i)
+                    c += (long double)B / h_primes[i] + 1;
+                bk_cap = c;
+                bk_cap_B = B;
+                bk_cap_np = h_primes.size();
+            }
+            const long double cap = bk_cap;
+            if (cap >= 4.0e9L) {
+                set_error_text("too many bucketed multiples per block; use a smaller block");
+                return MERTENS_EINVAL;
+            }
+            RCCHK(ensure(bk_cnt, (size_t)BK_WGS * (B / SEG) * 4));
+            RCCHK(ensure(bk_start, (B / SEG + 1) * 4));
+            RCCHK(ensure(bk_buf, (size_t)cap * 4 + 64));
+        }
         RCCHK(ensure(carry, 64));  // M(y1 - 1) at byte 0, segment ticket at byte 8
         RCCHK(ensure(bp_cur, ((size_t)nslots + MAX_WINDOWS) * sizeof(BlockParams)));
         RCCHK(ensure(bp_index, 64));
@@ -288,6 +312,11 @@ struct SieveState {
         b.n_small = count_primes_upto(SMALL_P - 1);
         // primes up to sqrt(y2) decide mu on the block (and every p < SMALL_P)
         b.n_sieve = count_primes_upto(std::max<uint64_t>(ceil_sqrt_host(y2), SMALL_P));
+        const uint32_t n_mid = count_primes_upto(SEG);
+        b.n_bucket = (b.n_sieve > n_mid && b.n_sieve - n_mid >= bucket_min) ? n_mid : b.n_sieve;
+        b.bk_cnt = bk_cnt.as<uint32_t>();
+        b.bk_start = bk_start.as<uint32_t>();
+        b.bk_buf = bk_buf.as<uint32_t>();
         b.n_sq = count_primes_upto(isqrt_host(y2));
         b.n_sq_lds = std::min(count_primes_upto(SQ_LDS_P), b.n_sq);
         b.pat_off = (uint32_t)(y1 % PAT);
@@ -325,7 +354,7 @@ struct SieveState {
         p.n_sq_lds = b.n_sq_lds;
         p.pat_off = b.pat_off;
         p.n_sieve = b.n_sieve;
-        p.pad = 0;
+        p.n_bucket = b.n_bucket;
         return p;
     }
 
@@ -338,6 +367,9 @@ struct SieveState {
         b.n_sq_lds = 0;
         b.n_sq = (uint32_t)h_primes.size();
         b.n_sieve = (uint32_t)h_primes.size();
+        // capture the bucket kernels whenever some block may use them
+        const uint32_t n_mid = count_primes_upto(SEG);
+        b.n_bucket = (b.n_sieve > n_mid && b.n_sieve - n_mid >= bucket_min) ? n_mid : b.n_sieve;
         return b;
     }
 
@@ -351,6 +383,7 @@ struct SieveState {
             HIPCHK(launch_block_set(params_of(b), const_cast<BlockParams *>(b.bp), s));
         HIPCHK(launch_block_setup(b, s));
         HIPCHK(launch_square_buckets(b, s));
+        HIPCHK(launch_prime_buckets(b, s));
         if (between)
             HIPCHK(hipEventRecord(between, s));
         HIPCHK(launch_sieve(b, s));
@@ -1402,6 +1435,10 @@ int mertens_set_param(const char *key, double value)
         if (!(value >= 0 && value <= 1024) || value != (double)(int)value)
             return MERTENS_EINVAL;
         g.tune.kbal = (uint32_t)value;
+    } else if (!strcmp(key, "bucket_min")) {
+        if (!(value >= 1 && value <= 4e9))
+            return MERTENS_EINVAL;
+        g.ss.bucket_min = (uint32_t)value;
     } else if (!strcmp(key, "rl_fast")) {
         if (!(value == 0.0 || value == 1.0))
             return MERTENS_EINVAL;

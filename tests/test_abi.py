@@ -41,7 +41,8 @@ def test_bad_arguments_without_gpu():
     assert lib.mertens_set_param(b"ychunk", float(1 << 21)) == mt.EINVAL  # fp64 sums inexact
     for key, bad in ((b"sieve_ahead", 0.0), (b"sieve_ahead", 257.0), (b"rl_fast", 2.0),
                      (b"update_window", 16.0), (b"update_window", 27.5), (b"kbal", -1.0),
-                     (b"kbal", 2.5), (b"klchunk", 256.0), (b"graph", 0.5)):
+                     (b"kbal", 2.5), (b"klchunk", 256.0), (b"graph", 0.5),
+                     (b"bucket_min", 0.0)):
         assert lib.mertens_set_param(key, bad) == mt.EINVAL, key
     # divisor outside [1, 2^32)
     n = np.array([5], dtype=np.uint64)

@@ -58,8 +58,9 @@ def test_sieve_mu_and_M_from_zero(mt):
 
 
 @pytest.mark.parametrize("y1", [10**9 - 70_000, 2**40 - 1000, 10**12 + 7, 10**15 - 200_001,
-                                11609864264058592345 // 1000])
+                                11609864264058592345 // 1000, 2**50 + 3 * 2**17 + 5])
 def test_sieve_windows(mt, y1):
+    mt.set_param("bucket_min", 1 << 14)
     count = 300_000
     mu, sums = mt.debug_mu(y1, count)
     ref = oracle.mu_range(y1, y1 + count - 1)
@@ -117,6 +118,8 @@ def test_n1e12_and_byproducts(mt):
     (10**8, 1 << 20, {"rl_fast": 0, "sieve_ahead": 64}),
     # balanced explicit-k runs for every tile the 8 x 8 walk would use badly
     (10**8, 1 << 26, {"kbal": 64}),
+    # every prime above 2^17 through per-segment buckets
+    (10**8, 1 << 24, {"bucket_min": 1}),
 ])
 def test_n1e12_invariance(mt, u, block, params):
     g = GOLDEN["n1e12"]
