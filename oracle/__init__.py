@@ -12,8 +12,10 @@ Tiers (see the C file for the paper passages each follows):
   order (Section 1 definition of M).
 * O2 ``mertens_identity`` -- the Section 2 identity with a threshold t,
   evaluated recursively on top of an O1 table M(0..T).
+* O3 ``interval`` -- Section 6: M over [a, b] from an exact M(a) and the O1
+  sieve, with the extremes of M(n)/sqrt(n) compared exactly.
 
-Parity pins for both tiers live in ``tests/test_oracle_pins.py``.
+Parity pins for every tier live in ``tests/test_oracle_pins.py``.
 """
 from __future__ import annotations
 
@@ -55,10 +57,12 @@ class OracleLib:
         lib.oracle_mertens_table.argtypes = [u64, ctypes.POINTER(ctypes.c_int32)]
         lib.oracle_mertens_many.argtypes = [ctypes.POINTER(ctypes.c_uint64), ctypes.c_size_t, i64p]
         lib.oracle_mertens_identity.argtypes = [u64, ctypes.POINTER(ctypes.c_int32), u64, i64p, i64p, u64]
+        lib.oracle_interval.argtypes = [u64, u64, ctypes.c_int64, i64p,
+                                        ctypes.POINTER(ctypes.c_uint64), i64p]
         lib.oracle_isqrt.argtypes = [u64]
         lib.oracle_isqrt.restype = u64
         for f in ("oracle_mu_range", "oracle_mertens_table", "oracle_mertens_many",
-                  "oracle_mertens_identity"):
+                  "oracle_mertens_identity", "oracle_interval"):
             getattr(lib, f).restype = ctypes.c_int
         self.lib = lib
 
@@ -97,6 +101,16 @@ class OracleLib:
         return int(mn.value), byp[:L].copy()
 
 
+    def interval(self, a: int, b: int, m_a: int) -> dict:
+        """O3: from M(a), M(b) and the extremes of M(n)/sqrt(n) over n in [a, b]."""
+        m_b = ctypes.c_int64(0)
+        n_ext = (ctypes.c_uint64 * 2)()
+        m_ext = (ctypes.c_int64 * 2)()
+        _check(self.lib.oracle_interval(a, b, m_a, ctypes.byref(m_b), n_ext, m_ext), "interval")
+        return {"m_b": int(m_b.value), "n_min": int(n_ext[0]), "m_min": int(m_ext[0]),
+                "n_max": int(n_ext[1]), "m_max": int(m_ext[1])}
+
+
 def default() -> OracleLib:
     global _default
     if _default is None:
@@ -116,6 +130,10 @@ def mertens_table(N: int) -> np.ndarray:
 
 def mertens_many(ns) -> np.ndarray:
     return default().mertens_many(ns)
+
+
+def interval(a: int, b: int, m_a: int) -> dict:
+    return default().interval(a, b, m_a)
 
 
 def isqrt(v: int) -> int:

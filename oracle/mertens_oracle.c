@@ -8,7 +8,7 @@
  * correct restatement of the definitions in "Computing the Mertens function
  * on a GPU" (Kuznetsov, arXiv:1108.0135).
  *
- * Two tiers:
+ * Three tiers:
  *
  *   O1  oracle_mu_range / oracle_mertens_table / oracle_mertens_many
  *       The exact block sieve of Section 3 (Implementation), the "naive"
@@ -28,6 +28,11 @@
  *       printed form of this rewrite is garbled (its floor arguments are
  *       written n/(xt)); the form above is the reading used here, and it is
  *       exact for every 2 <= t <= m.
+ *
+ *   O3  oracle_interval
+ *       Section 6: M(n) for every n in [a, b] from an exact M(a) plus the O1
+ *       sieve over (a, b], and the smallest and largest M(n)/sqrt(n) there,
+ *       compared exactly in integers.
  *
  * Integer conventions: hardware '/' only; products and partial sums of the
  * recursion are taken in wrapping uint64 and reinterpreted as int64 at the
@@ -335,3 +340,90 @@ int oracle_mertens_identity(uint64_t n, const int32_t *tab, uint64_t T,
 
 /* floor(sqrt(v)), exported so tests can check table sizing. */
 uint64_t oracle_isqrt(uint64_t v) { return isqrt_u64(v); }
+
+/*
+ * O3: Section 6, localizing an extreme between exact grid points.  Given
+ * the exact value M(a) at a grid point a, every M(n) for n in [a, b] is
+ * M(a) plus the sum of mu over (a, n] (the O1 sieve, Section 1 definition
+ * of M), and the extremes of M(n)/sqrt(n) over the interval are read off
+ * those values.
+ *
+ * Ratio order without rounding: for n1, n2 >= 1, M1/sqrt(n1) < M2/sqrt(n2)
+ * holds when sign(M1) < sign(M2); for equal positive signs exactly when
+ * M1^2 n2 < M2^2 n1; for equal negative signs exactly when M1^2 n2 > M2^2 n1;
+ * never when both are zero.  Products are taken in unsigned 128-bit
+ * arithmetic, which holds them while |M| < 2^32 (else ORACLE_ERANGE).  On
+ * equal ratios the smaller n is kept.
+ *
+ * Outputs: *m_b = M(b); n_ext[0], m_ext[0] = the n in [a, b] with the
+ * smallest M(n)/sqrt(n) and M there; n_ext[1], m_ext[1] the same for the
+ * largest.  1 <= a <= b.
+ */
+static int ratio_less(int64_t m1, uint64_t n1, int64_t m2, uint64_t n2)
+{
+    int s1 = (m1 > 0) - (m1 < 0), s2 = (m2 > 0) - (m2 < 0);
+    if (s1 != s2)
+        return s1 < s2;
+    if (s1 == 0)
+        return 0;
+    uint64_t a1 = (uint64_t)(m1 < 0 ? -m1 : m1), a2 = (uint64_t)(m2 < 0 ? -m2 : m2);
+    unsigned __int128 l = (unsigned __int128)(a1 * a1) * n2;
+    unsigned __int128 r = (unsigned __int128)(a2 * a2) * n1;
+    return s1 > 0 ? l < r : l > r;
+}
+
+int oracle_interval(uint64_t a, uint64_t b, int64_t m_a, int64_t *m_b, uint64_t *n_ext,
+                    int64_t *m_ext)
+{
+    if (!m_b || !n_ext || !m_ext || a == 0 || b < a)
+        return ORACLE_EINVAL;
+    const int64_t lim = (int64_t)1 << 32;
+    int64_t m = m_a;
+    uint64_t nmin = a, nmax = a;
+    int64_t mmin = m_a, mmax = m_a;
+    if (m >= lim || m <= -lim)
+        return ORACLE_ERANGE;
+    size_t np;
+    uint32_t *pr = primes_upto(ceil_sqrt(b), &np);
+    uint64_t *mag = (uint64_t *)malloc(SUB_BLOCK * sizeof(uint64_t));
+    uint8_t *neg = (uint8_t *)malloc(SUB_BLOCK);
+    int8_t *mu = (int8_t *)malloc(SUB_BLOCK);
+    if (!pr || !mag || !neg || !mu) {
+        free(pr); free(mag); free(neg); free(mu);
+        return ORACLE_ENOMEM;
+    }
+    int rc = ORACLE_OK;
+    for (uint64_t c = a; c < b && rc == ORACLE_OK; c += SUB_BLOCK) {
+        /* mu over (c, c2] */
+        uint64_t c2 = (b - c <= SUB_BLOCK) ? b : c + SUB_BLOCK;
+        mu_block(c + 1, c2, pr, np, mag, neg, mu);
+        for (uint64_t i = 0; i < c2 - c; i++) {
+            uint64_t n = c + 1 + i;
+            m += mu[i];
+            if (m >= lim || m <= -lim) {
+                rc = ORACLE_ERANGE;
+                break;
+            }
+            /* n only grows, so a tie keeps the earlier n */
+            if (ratio_less(m, n, mmin, nmin)) {
+                nmin = n;
+                mmin = m;
+            }
+            if (ratio_less(mmax, nmax, m, n)) {
+                nmax = n;
+                mmax = m;
+            }
+        }
+        if (c2 == b)
+            break;
+    }
+    free(pr); free(mag); free(neg); free(mu);
+    if (rc != ORACLE_OK)
+        return rc;
+    *m_b = m;
+    n_ext[0] = nmin;
+    m_ext[0] = mmin;
+    n_ext[1] = nmax;
+    m_ext[1] = mmax;
+    return ORACLE_OK;
+}

@@ -9,7 +9,10 @@ None of these compare the oracle with itself.  They use
 * the printed extreme ratio |M(n)|/sqrt(n) = 0.570591 at n = 7766842813
   (Section 1), which fixes |M(7766842813)| uniquely,
 * agreement of the two oracle tiers, which share nothing but the O1 table
-  at small arguments.
+  at small arguments,
+* for the interval tier (Section 6), brute-force extremes of M(n)/sqrt(n)
+  with decimal square roots over trial-division mu, and the printed extreme
+  above as the extreme of a window around it.
 
 ``test_planted_mistakes`` rebuilds the oracle with one plausible mistake at a
 time (textual edits of a copy of the C source, compiled in a temp dir) and
@@ -19,6 +22,8 @@ from __future__ import annotations
 
 import math
 import os
+from decimal import Decimal, getcontext
+from fractions import Fraction
 import shutil
 import subprocess
 
@@ -158,8 +163,102 @@ def pin_paper_extreme_ratio(lib):
     assert lo == hi == abs(m)
 
 
+def _extremes_decimal(ms, ns):
+    """(argmin, argmax) of m/sqrt(n) with 50-digit decimal square roots; values
+    within 1e-40 of each other count as equal and the smaller n is kept."""
+    getcontext().prec = 50
+    r = [Decimal(m) / Decimal(n).sqrt() for m, n in zip(ms, ns)]
+    eps = Decimal("1e-40")
+    lo = hi = 0
+    for i in range(1, len(r)):
+        if r[i] < r[lo] - eps:
+            lo = i
+        if r[i] > r[hi] + eps:
+            hi = i
+    return ns[lo], ns[hi]
+
+
+_MU_TRIAL_20K = None
+
+
+def _mertens_trial(N: int) -> list:
+    """M(0..N) from textbook trial-division mu (N <= 20000), cached."""
+    global _MU_TRIAL_20K
+    if _MU_TRIAL_20K is None:
+        run, out = 0, [0]
+        for y in range(1, 20001):
+            run += mu_trial(y)
+            out.append(run)
+        _MU_TRIAL_20K = out
+    return _MU_TRIAL_20K[: N + 1]
+
+
+def pin_interval_brute(lib):
+    # Section 6: values on [a, b] from M(a) and the sieve; extremes by brute force
+    M = _mertens_trial(20000)
+    rng = np.random.default_rng(5)
+    cases = [(1, 1), (1, 10), (1, 20000), (2, 2), (13, 13)]
+    for _ in range(30):
+        a = int(rng.integers(1, 19000))
+        cases.append((a, a + int(rng.integers(0, 1000))))
+    # ties: an interval between two zeros of M over which M never rises above
+    # zero (largest ratio 0 at both ends), and the same below zero
+    zeros = [n for n in range(1, 20001) if M[n] == 0]
+    for sgn in (1, -1):
+        for z1, z2 in zip(zeros, zeros[1:]):
+            if z2 > z1 + 2 and all(sgn * M[n] <= 0 for n in range(z1, z2 + 1)):
+                cases.append((z1, z2))
+                break
+    for a, b in cases:
+        got = lib.interval(a, b, M[a])
+        ns = list(range(a, b + 1))
+        nmin, nmax = _extremes_decimal([M[n] for n in ns], ns)
+        assert got["m_b"] == M[b], (a, b)
+        assert (got["n_min"], got["m_min"]) == (nmin, M[nmin]), (a, b)
+        assert (got["n_max"], got["m_max"]) == (nmax, M[nmax]), (a, b)
+
+
+def pin_interval_long(lib):
+    # an interval across many oracle sub-blocks, against the O1 table and a
+    # float filter plus exact integer comparison done here
+    a, b = 1_000_003, 3_500_000
+    tab = lib.mertens_table(b).astype(np.int64)
+    got = lib.interval(a, b, int(tab[a]))
+    assert got["m_b"] == int(tab[b])
+    ns = np.arange(a, b + 1)
+    ms = tab[a:]
+    r = ms / np.sqrt(ns.astype(np.float64))
+    def order(t):  # sign(m) m^2 / n orders pairs exactly as m / sqrt(n)
+        m, n = t
+        return ((m > 0) - (m < 0)) * Fraction(m * m, n)
+
+    for key, sgn in (("n_min", 1), ("n_max", -1)):
+        best = np.min(sgn * r)
+        cand = np.nonzero(np.abs(sgn * r - best) <= 1e-9 * abs(best) + 1e-12)[0]
+        pairs = [(int(ms[i]), int(ns[i])) for i in cand]
+        want = min(pairs, key=lambda t: (sgn * order(t), t[1]))
+        assert got[key] == want[1], key
+
+
+def pin_interval_paper_extreme(lib):
+    # Section 1: |M(n)|/sqrt(n) = 0.570591 at n = 7766842813 is the largest
+    # known ratio, so it is the extreme of any window around it
+    n0 = 7766842813
+    a, b = n0 - 2**16, n0 + 2**16
+    tab = lib.mertens_table(5_000_000)
+    m_a, _ = lib.identity(a, tab)
+    m_b, _ = lib.identity(b, tab)
+    got = lib.interval(a, b, m_a)
+    assert got["m_b"] == m_b
+    far = max((got["n_min"], got["m_min"]), (got["n_max"], got["m_max"]),
+              key=lambda t: abs(t[1]) / math.sqrt(t[0]))
+    assert far[0] == n0
+    assert round(abs(far[1]) / math.sqrt(n0), 6) == 0.570591
+
+
 ALL_PINS = [pin_mu_textbook, pin_mu_high_windows, pin_small_values, pin_identity,
-            pin_tiers_agree, pin_byproducts, pin_paper_extreme_ratio]
+            pin_tiers_agree, pin_byproducts, pin_paper_extreme_ratio, pin_interval_brute,
+            pin_interval_long, pin_interval_paper_extreme]
 
 
 # ---------------------------------------------------------------- tests
@@ -199,6 +298,13 @@ MUTANTS = [
      "for (uint64_t x = 2; x < xmax; x++)"),
     ("second sum bound short", "for (uint64_t y = 1; y < t; y++)",
      "for (uint64_t y = 1; y + 1 < t; y++)"),
+    ("negative ratios ordered like positive ones", "return s1 > 0 ? l < r : l > r;",
+     "return l < r;"),
+    ("ties keep the later n", "if (ratio_less(mmax, nmax, m, n)) {",
+     "if (!ratio_less(m, n, mmax, nmax)) {"),
+    ("interval chunk starts one early", "mu_block(c + 1, c2, pr, np, mag, neg, mu);",
+     "mu_block(c, c2 - 1, pr, np, mag, neg, mu);"),
+    ("squares compared without the other n", "* n2;\n", "* n1;\n"),
 ]
 
 
