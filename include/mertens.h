@@ -189,6 +189,33 @@ const char *mertens_strerror(int code);
 const char *mertens_last_error(void);
 
 /*
+ * mertens_interval -- every M(n) for n in [a, b] from one exact value, and
+ * where M(n)/sqrt(n) is smallest and largest there (Section 6: once M is
+ * known exactly at grid points, the gaps between them are covered by direct
+ * sieving and the local extreme is read off the values).
+ *   a, b    1 <= a <= b <= 2^64 - 2^32.
+ *   m_a     M(a) if the caller knows it (e.g. from an earlier mertens_query),
+ *           else NULL: the library first runs mertens_query on a, which
+ *           replaces the arrays mertens_byproducts reads.
+ *   m_b     out: M(b) (may be NULL).
+ *   n_ext   out (may be NULL): n_ext[0] = the n in [a, b] with the smallest
+ *           M(n)/sqrt(n), n_ext[1] = the n with the largest; equal ratios
+ *           give the smaller n.  The comparison is exact (integer products,
+ *           no rounding).
+ *   m_ext   out (may be NULL): M(n_ext[0]), M(n_ext[1]).
+ *   values  out (may be NULL): M(n) for n = a..b into values[0..b-a]; needs
+ *           cap >= b - a + 1 and b - a + 1 <= 2^28.
+ * The sweep sieves mu over [a - (a mod 2^17), b] in blocks (device primes up
+ * to ceil(sqrt(b)), the ones above 2^17 through per-segment buckets), runs
+ * the M(y) prefix from zero, and shifts it by M(a) minus the prefix at a.
+ * mertens_stats afterwards: sieved_y, blocks, ms_sieve (sieve and buckets),
+ * ms_update (the interval reductions), ms_total; the other slots 0.
+ * Returns 0, MERTENS_EINVAL, MERTENS_ENOMEM, MERTENS_ENODEV, MERTENS_EIO.
+ */
+int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, uint64_t *n_ext,
+                     int64_t *m_ext, int64_t *values, size_t cap);
+
+/*
  * Diagnostics used by the test suite.
  *
  * mertens_debug_div -- exact floor(n[i] / d[i]) for d[i] in [1, 2^32) by the

@@ -30,8 +30,14 @@ constexpr uint32_t SQ_BUCKET = 64;
 // them, BK_WGS workgroups (each a fixed share of those primes) list their
 // multiples into per-segment buckets in two passes (count, fill), so the
 // sieve reads its hits instead of testing every such prime.
-constexpr uint32_t BK_WGS = 512, BK_THREADS = 1024;
+#ifndef MERTENS_BK_WGS
+#define MERTENS_BK_WGS 512
+#endif
+constexpr uint32_t BK_WGS = MERTENS_BK_WGS, BK_THREADS = 1024;
 constexpr uint32_t MAX_SEGS = (1u << 31) / SEG;  // segments of the longest block
+// Interval sweep: workgroups of the extreme reduction (each keeps its own
+// running candidates across the blocks of one interval).
+constexpr uint32_t IV_WGS = 2048, IV_THREADS = 256;
 // First index of the prime table that is sieved (table starts at 5; the
 // pattern covers 5, 7, 11, 13, so sieving starts at 17 = index 4).
 constexpr uint32_t FIRST_SIEVED = 4;
@@ -50,6 +56,8 @@ struct BlockParams {
     uint32_t nseg, n_sq, n_sq_lds, pat_off;
     uint32_t n_sieve;
     uint32_t n_bucket;  // primes with index in [n_bucket, n_sieve) reach the sieve through buckets
+    uint32_t n_lane;    // bucketed primes from this index on have at most 64 multiples per block
+    uint32_t n_sq_lane; // squares from this index on have at most 64 multiples per block
 };
 
 // One y-block [y1, y2] of the sweep.  The scalar fields below mirror *bp on
@@ -62,7 +70,9 @@ struct BlockArgs {
     uint32_t n_sieve;   // primes with index < n_sieve are sieved (p <= max(sqrt(y2), SMALL_P))
     uint32_t n_sq_lds;  // primes with index < n_sq_lds have p <= SQ_LDS_P
     uint32_t n_sq;      // primes with index < n_sq have p^2 <= y2
+    uint32_t n_sq_lane; // ... of which those from n_sq_lane on (p^2 > span / 64) take a lane each
     uint32_t n_bucket;  // primes with index in [n_bucket, n_sieve) (all > SEG) are bucketed
+    uint32_t n_lane;    // ... of which those from n_lane on (> span / 64) are walked per lane
     uint32_t pat_off;   // y1 mod PAT
     uint2 *pres;              // {p, y1 mod p}: primes >= 5 ascending, residue per block
     uint64_t *res2;           // y1 mod p^2    (per block)
@@ -142,6 +152,20 @@ hipError_t launch_collect(const QueryArgs &q, int64_t *out, hipStream_t s);
 // out[c-1] = A entry of (c, floor(n_qi/c)) for c = 1..count (keyed group member qi)
 hipError_t launch_keyed_byproducts(const QueryArgs &q, uint32_t qi, uint64_t count, int64_t *out,
                                    hipStream_t s);
+// Interval sweep (records of the current block, relative to *off):
+// *off = m_a - (record value at a)
+hipError_t launch_interval_base(const BlockArgs &b, uint64_t a, int64_t m_a, int64_t *off,
+                                hipStream_t s);
+// running extremes of M(n)/sqrt(n) over n in [lo, hi] into part[IV_WGS][4]
+// = {n_min, M(n_min), n_max, M(n_max)} (n = 0: none yet)
+hipError_t launch_interval_extreme(const BlockArgs &b, uint64_t lo, uint64_t hi,
+                                   const int64_t *off, uint64_t *part, hipStream_t s);
+// dst[i] = M(lo + i) for i < count
+hipError_t launch_interval_values(const BlockArgs &b, uint64_t lo, uint64_t count,
+                                  const int64_t *off, int64_t *dst, hipStream_t s);
+// res[0..3] = the reduced extremes of part, res[4] = M(n_end) (n_end in block b)
+hipError_t launch_interval_final(const BlockArgs &b, const uint64_t *part, uint64_t n_end,
+                                 const int64_t *off, int64_t *res, hipStream_t s);
 hipError_t launch_debug_div(const uint64_t *n, const uint64_t *d, uint64_t *q, size_t count,
                             hipStream_t s);
 hipError_t launch_debug_mu(const BlockArgs &b, uint64_t y_first, uint32_t count, int8_t *mu,

@@ -208,9 +208,11 @@ __device__ inline BlockArgs load_block(BlockArgs b)
     b.nseg = p.nseg;
     b.n_sq = p.n_sq;
     b.n_sq_lds = p.n_sq_lds;
+    b.n_sq_lane = p.n_sq_lane;
     b.pat_off = p.pat_off;
     b.n_sieve = p.n_sieve;
     b.n_bucket = p.n_bucket;
+    b.n_lane = p.n_lane;
     return b;
 }
 
@@ -350,40 +352,64 @@ hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s)
     return hipGetLastError();
 }
 
-// Large squares: one wave per prime p (SQ_LDS_P < p, p^2 <= y2), lane j
-// taking multiples j, j + 64, ... of p^2 in the block (at most B / 2^20 + 1
-// of them), lists every multiple in its segment's bucket.
+// Large squares (SQ_LDS_P < p, p^2 <= y2; p^2 > 2^20 > SEG, so at most one
+// multiple per segment), each multiple listed in its segment's bucket.  Up
+// to n_sq_lane one wave per prime, lane j taking multiples j, j + 64, ... of
+// p^2 in the block; from n_sq_lane on (at most 64 multiples) one lane each.
+__device__ inline void square_hit(const BlockArgs &b, uint64_t o)
+{
+    const uint32_t sg = (uint32_t)(o / SEG);
+    const uint32_t k = atomicAdd(&b.sq_cnt[sg], 1u);
+    if (k < SQ_BUCKET)
+        b.sq_buf[(uint64_t)sg * SQ_BUCKET + k] = (uint32_t)(o % SEG);
+}
+
 __global__ void k_square_buckets(BlockArgs b_in)
 {
     const BlockArgs b = load_block(b_in);
     const uint32_t i = b.n_sq_lds + __builtin_amdgcn_readfirstlane(
                                         blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6));
+    if (i >= b.n_sq_lane)
+        return;
+    const uint64_t p = b.pres[i].x;
+    const uint64_t d = p * p;
+    const uint64_t r2 = b.res2[i];
+    const uint64_t span = b.y2 - b.y1;
+    for (uint64_t o = (r2 ? d - r2 : 0) + lane_id() * d; o <= span; o += 64 * d)
+        square_hit(b, o);
+}
+
+__global__ void k_square_buckets_lane(BlockArgs b_in)
+{
+    const BlockArgs b = load_block(b_in);
+    const uint64_t i = b.n_sq_lane + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= b.n_sq)
         return;
     const uint64_t p = b.pres[i].x;
     const uint64_t d = p * p;
     const uint64_t r2 = b.res2[i];
     const uint64_t span = b.y2 - b.y1;
-    for (uint64_t o = (r2 ? d - r2 : 0) + lane_id() * d; o <= span; o += 64 * d) {
-        const uint32_t sg = (uint32_t)(o / SEG);
-        const uint32_t k = atomicAdd(&b.sq_cnt[sg], 1u);
-        if (k < SQ_BUCKET)
-            b.sq_buf[(uint64_t)sg * SQ_BUCKET + k] = (uint32_t)(o % SEG);
-    }
+    for (uint64_t o = r2 ? d - r2 : 0; o <= span; o += d)
+        square_hit(b, o);
 }
 
 hipError_t launch_square_buckets(const BlockArgs &b, hipStream_t s)
 {
-    if (b.n_sq <= b.n_sq_lds)
-        return hipSuccess;
-    const uint32_t n = b.n_sq - b.n_sq_lds;  // waves
-    hipLaunchKernelGGL(k_square_buckets, dim3((n + 3) / 4), dim3(256), 0, s, b);
+    if (b.n_sq_lane > b.n_sq_lds) {
+        const uint32_t n = b.n_sq_lane - b.n_sq_lds;  // waves
+        hipLaunchKernelGGL(k_square_buckets, dim3((n + 3) / 4), dim3(256), 0, s, b);
+    }
+    if (b.n_sq > b.n_sq_lane) {
+        const uint32_t n = b.n_sq - b.n_sq_lane;  // lanes
+        hipLaunchKernelGGL(k_square_buckets_lane, dim3((n + 255) / 256), dim3(256), 0, s, b);
+    }
     return hipGetLastError();
 }
 
-// Bucketed primes p > SEG (index in [n_bucket, n_sieve)): wave v of
-// workgroup w takes the primes n_bucket + w * 16 + v + j * BK_WGS * 16, its
-// lanes the multiples lane, lane + 64, ... (at most B / p <= 2^14 of them).
+// Bucketed primes p > SEG (index in [n_bucket, n_sieve)): up to n_lane, wave
+// v of workgroup w takes the primes n_bucket + w * 16 + v + j * BK_WGS * 16,
+// its lanes the multiples lane, lane + 64, ... (at most B / p <= 2^14 of
+// them); the primes from n_lane on (p > span / 64) take one lane each.
 // Pass 1 counts the workgroup's hits per segment in LDS and stores the
 // counts; k_bucket_columns / k_bucket_starts turn them into each
 // workgroup's first entry per segment; pass 2 writes the entries there.
@@ -408,12 +434,27 @@ __global__ __launch_bounds__(BK_THREADS) void k_prime_buckets(BlockArgs b_in)
     constexpr uint32_t WAVES = BK_THREADS / 64;
     const uint32_t lane = lane_id();
     const uint32_t v = __builtin_amdgcn_readfirstlane(tid >> 6);
-    for (uint64_t i = b.n_bucket + (uint64_t)w * WAVES + v; i < b.n_sieve;
+    for (uint64_t i = b.n_bucket + (uint64_t)w * WAVES + v; i < b.n_lane;
          i += (uint64_t)BK_WGS * WAVES) {
         const uint2 e = b.pres[i];
         const uint64_t p = e.x;
         const uint32_t lp = log_prime(e.x);
         for (uint64_t o = (e.y ? p - e.y : 0) + lane * p; o < span; o += 64 * p) {
+            if (FILL) {
+                const uint32_t k = atomicAdd(&cnt[o / SEG], 1u);
+                b.bk_buf[k] = bucket_entry(o, lp);
+            } else {
+                atomicAdd(&cnt[o / SEG], 1u);
+            }
+        }
+    }
+    // primes above span / 64 (at most 64 multiples in the block): one lane each
+    for (uint64_t i = b.n_lane + (uint64_t)w * BK_THREADS + tid; i < b.n_sieve;
+         i += (uint64_t)BK_WGS * BK_THREADS) {
+        const uint2 e = b.pres[i];
+        const uint64_t p = e.x;
+        const uint32_t lp = log_prime(e.x);
+        for (uint64_t o = e.y ? p - e.y : 0; o < span; o += p) {
             if (FILL) {
                 const uint32_t k = atomicAdd(&cnt[o / SEG], 1u);
                 b.bk_buf[k] = bucket_entry(o, lp);
@@ -1666,6 +1707,253 @@ hipError_t launch_keyed_byproducts(const QueryArgs &q, uint32_t qi, uint64_t cou
 hipError_t launch_collect(const QueryArgs &q, int64_t *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_collect, dim3((q.nq + 255) / 256), dim3(256), 0, s, q, out);
+    return hipGetLastError();
+}
+
+// ====================================================================
+// Interval sweep (Section 6): every M(n) on [a, b] from an exact M(a) and
+// the sieve records of the blocks covering [a, b], and the n where
+// M(n)/sqrt(n) is smallest and largest.  The blocks are sieved with the
+// carry starting at 0, so a record holds M(y) - M(start - 1); *off turns
+// that into M(y).
+// ====================================================================
+
+// |m|^2 n as a 192-bit integer (|m| < 2^63, n < 2^64), low word first.
+struct U192 {
+    uint64_t w0, w1, w2;
+};
+
+__device__ inline U192 sq_times(uint64_t a, uint64_t n)
+{
+    const uint64_t l = a * a, h = __umul64hi(a, a);  // a^2 = h 2^64 + l
+    U192 r;
+    r.w0 = l * n;
+    const uint64_t t = __umul64hi(l, n);
+    r.w1 = t + h * n;
+    r.w2 = __umul64hi(h, n) + (r.w1 < t ? 1u : 0u);
+    return r;
+}
+
+__device__ inline int cmp192(const U192 &x, const U192 &y)
+{
+    if (x.w2 != y.w2)
+        return x.w2 < y.w2 ? -1 : 1;
+    if (x.w1 != y.w1)
+        return x.w1 < y.w1 ? -1 : 1;
+    if (x.w0 != y.w0)
+        return x.w0 < y.w0 ? -1 : 1;
+    return 0;
+}
+
+// Sign of m1 / sqrt(n1) - m2 / sqrt(n2) (n1, n2 >= 1), without rounding:
+// signs first, then m1^2 n2 against m2^2 n1 (reversed for negative m).
+__device__ inline int ratio_cmp(int64_t m1, uint64_t n1, int64_t m2, uint64_t n2)
+{
+    const int s1 = (m1 > 0) - (m1 < 0), s2 = (m2 > 0) - (m2 < 0);
+    if (s1 != s2)
+        return s1 < s2 ? -1 : 1;
+    if (s1 == 0)
+        return 0;
+    const uint64_t a1 = m1 < 0 ? 0 - (uint64_t)m1 : (uint64_t)m1;
+    const uint64_t a2 = m2 < 0 ? 0 - (uint64_t)m2 : (uint64_t)m2;
+    int c;
+    if ((a1 | a2) >> 32 == 0) {  // squares fit 64 bits: 128-bit products
+        const uint64_t q1 = a1 * a1, q2 = a2 * a2;
+        const uint64_t h1 = __umul64hi(q1, n2), h2 = __umul64hi(q2, n1);
+        const uint64_t l1 = q1 * n2, l2 = q2 * n1;
+        c = h1 != h2 ? (h1 < h2 ? -1 : 1) : (l1 != l2 ? (l1 < l2 ? -1 : 1) : 0);
+    } else {
+        c = cmp192(sq_times(a1, n2), sq_times(a2, n1));
+    }
+    return s1 > 0 ? c : -c;
+}
+
+// Candidate (n1, m1) beats (n2, m2) for the minimum (dir = 1) or the
+// maximum (dir = -1) of m / sqrt(n); n = 0 is "none"; equal ratios keep the
+// smaller n.  A total order, so any reduction order gives the same winner.
+__device__ inline bool beats(uint64_t n1, int64_t m1, uint64_t n2, int64_t m2, int dir)
+{
+    if (n1 == 0)
+        return false;
+    if (n2 == 0)
+        return true;
+    const int c = ratio_cmp(m1, n1, m2, n2) * dir;
+    return c < 0 || (c == 0 && n1 < n2);
+}
+
+struct Extremes {
+    uint64_t nmin, nmax;
+    int64_t mmin, mmax;
+};
+
+__device__ inline void merge_extremes(Extremes &e, const Extremes &o)
+{
+    if (beats(o.nmin, o.mmin, e.nmin, e.mmin, 1)) {
+        e.nmin = o.nmin;
+        e.mmin = o.mmin;
+    }
+    if (beats(o.nmax, o.mmax, e.nmax, e.mmax, -1)) {
+        e.nmax = o.nmax;
+        e.mmax = o.mmax;
+    }
+}
+
+__device__ inline Extremes wave_extremes(Extremes e)
+{
+    for (int o = 32; o >= 1; o >>= 1) {
+        Extremes t;
+        t.nmin = __shfl_xor(e.nmin, o, 64);
+        t.mmin = __shfl_xor(e.mmin, o, 64);
+        t.nmax = __shfl_xor(e.nmax, o, 64);
+        t.mmax = __shfl_xor(e.mmax, o, 64);
+        merge_extremes(e, t);
+    }
+    return e;
+}
+
+// Workgroup reduction of e (every thread passes its own); the result is
+// valid in thread 0.
+__device__ inline Extremes wg_extremes(Extremes e, Extremes *lds)
+{
+    e = wave_extremes(e);
+    const uint32_t wave = threadIdx.x >> 6;
+    if (lane_id() == 0)
+        lds[wave] = e;
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (uint32_t k = 1; k < blockDim.x / 64; ++k)
+            merge_extremes(e, lds[k]);
+    return e;
+}
+
+__global__ void k_interval_base(BlockArgs b_in, uint64_t a, int64_t m_a, int64_t *off)
+{
+    const BlockArgs b = load_block(b_in);
+    if (threadIdx.x == 0)
+        *off = m_a - M_at(b.words, a - b.y1);
+}
+
+hipError_t launch_interval_base(const BlockArgs &b, uint64_t a, int64_t m_a, int64_t *off,
+                                hipStream_t s)
+{
+    hipLaunchKernelGGL(k_interval_base, dim3(1), dim3(64), 0, s, b, a, m_a, off);
+    return hipGetLastError();
+}
+
+// One thread per 32-y record (grid-stride, so a thread meets its y in
+// increasing order, each after its current candidates): M(y) is the
+// record's value plus the running +-1 bits.  As a later y with an equal
+// ratio loses, a record can only hold a new minimum if the ratio bound
+// mlo / sqrt(y) (M at least the value before it minus its -1 count, y at the
+// end that makes the bound smallest) is strictly below the current one, and
+// likewise for the maximum; other records are skipped after that exact test.
+__global__ __launch_bounds__(IV_THREADS) void k_interval_extreme(BlockArgs b_in, uint64_t lo,
+                                                                 uint64_t hi, const int64_t *off,
+                                                                 uint64_t *part)
+{
+    const BlockArgs b = load_block(b_in);
+    __shared__ Extremes lds[IV_THREADS / 64];
+    const int64_t base = *off;
+    const uint64_t r0 = (lo - b.y1) >> 5, r1 = (hi - b.y1) >> 5;
+    Extremes e = {0, 0, 0, 0};
+    for (uint64_t r = r0 + (uint64_t)blockIdx.x * IV_THREADS + threadIdx.x; r <= r1;
+         r += (uint64_t)gridDim.x * IV_THREADS) {
+        const ulonglong2 rec = *reinterpret_cast<const ulonglong2 *>(b.words + 2 * r);
+        const uint32_t pos = (uint32_t)rec.x, neg = (uint32_t)(rec.x >> 32);
+        const uint64_t y0 = b.y1 + 32 * r;
+        const uint32_t jlo = y0 < lo ? (uint32_t)(lo - y0) : 0u;
+        const uint32_t jhi = hi - y0 < 31 ? (uint32_t)(hi - y0) : 31u;
+        const int64_t m0 = (int64_t)rec.y + base;
+        const int64_t mlo = m0 - __popc(neg), mhi = m0 + __popc(pos);
+        const uint64_t ylo = y0 + jlo, yhi = y0 + jhi;
+        const bool pmin = e.nmin == 0 || ratio_cmp(mlo, mlo < 0 ? ylo : yhi, e.mmin, e.nmin) < 0;
+        const bool pmax = e.nmax == 0 || ratio_cmp(mhi, mhi < 0 ? yhi : ylo, e.mmax, e.nmax) > 0;
+        if (!pmin && !pmax)
+            continue;
+        int64_t m = m0;
+        for (uint32_t j = 0; j <= jhi; ++j) {
+            m += (int64_t)((pos >> j) & 1u) - (int64_t)((neg >> j) & 1u);
+            if (j < jlo)
+                continue;
+            const uint64_t y = y0 + j;
+            // below a negative minimum / above a positive maximum only
+            if (pmin && (e.mmin >= 0 || m < e.mmin) && beats(y, m, e.nmin, e.mmin, 1)) {
+                e.nmin = y;
+                e.mmin = m;
+            }
+            if (pmax && (e.mmax <= 0 || m > e.mmax) && beats(y, m, e.nmax, e.mmax, -1)) {
+                e.nmax = y;
+                e.mmax = m;
+            }
+        }
+    }
+    e = wg_extremes(e, lds);
+    if (threadIdx.x == 0) {
+        uint64_t *pw = part + 4 * (size_t)blockIdx.x;
+        const Extremes prev = {pw[0], pw[2], (int64_t)pw[1], (int64_t)pw[3]};
+        merge_extremes(e, prev);
+        pw[0] = e.nmin;
+        pw[1] = (uint64_t)e.mmin;
+        pw[2] = e.nmax;
+        pw[3] = (uint64_t)e.mmax;
+    }
+}
+
+hipError_t launch_interval_extreme(const BlockArgs &b, uint64_t lo, uint64_t hi,
+                                   const int64_t *off, uint64_t *part, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_interval_extreme, dim3(IV_WGS), dim3(IV_THREADS), 0, s, b, lo, hi, off,
+                       part);
+    return hipGetLastError();
+}
+
+__global__ void k_interval_values(BlockArgs b_in, uint64_t lo, uint64_t count, const int64_t *off,
+                                  int64_t *dst)
+{
+    const BlockArgs b = load_block(b_in);
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        dst[i] = M_at(b.words, lo + i - b.y1) + *off;
+}
+
+hipError_t launch_interval_values(const BlockArgs &b, uint64_t lo, uint64_t count,
+                                  const int64_t *off, int64_t *dst, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_interval_values, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s,
+                       b, lo, count, off, dst);
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(IV_THREADS) void k_interval_final(BlockArgs b_in,
+                                                               const uint64_t *part,
+                                                               uint64_t n_end, const int64_t *off,
+                                                               int64_t *res)
+{
+    const BlockArgs b = load_block(b_in);
+    __shared__ Extremes lds[IV_THREADS / 64];
+    Extremes e = {0, 0, 0, 0};
+    for (uint32_t w = threadIdx.x; w < IV_WGS; w += IV_THREADS) {
+        const uint64_t *pw = part + 4 * (size_t)w;
+        const Extremes o = {pw[0], pw[2], (int64_t)pw[1], (int64_t)pw[3]};
+        merge_extremes(e, o);
+    }
+    e = wg_extremes(e, lds);
+    if (threadIdx.x == 0) {
+        res[0] = (int64_t)e.nmin;
+        res[1] = e.mmin;
+        res[2] = (int64_t)e.nmax;
+        res[3] = e.mmax;
+        res[4] = M_at(b.words, n_end - b.y1) + *off;
+    }
+}
+
+hipError_t launch_interval_final(const BlockArgs &b, const uint64_t *part, uint64_t n_end,
+                                 const int64_t *off, int64_t *res, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_interval_final, dim3(1), dim3(IV_THREADS), 0, s, b, part, n_end, off,
+                       res);
     return hipGetLastError();
 }
 

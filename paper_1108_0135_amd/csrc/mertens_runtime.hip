@@ -198,25 +198,49 @@ struct SieveState {
         have_pattern = false;
     }
 
-    // Sieving primes p in [5, limit] (plain Eratosthenes on odd numbers) and
-    // their device copy as {p, residue} pairs.  Grows only.
+    // Sieving primes p in [5, limit] (segmented Eratosthenes over odd
+    // numbers, 2^19 of them per segment, from the base primes up to
+    // sqrt(limit)) and their device copy as {p, residue} pairs.  Grows only.
     int ensure_primes(uint64_t limit)
     {
         if (limit <= psieve)
             return 0;
-        std::vector<uint8_t> comp(limit / 2 + 1, 0);  // comp[i] <=> 2i+1 composite
-        for (uint64_t i = 3; i * i <= limit; i += 2)
-            if (!comp[i / 2])
-                for (uint64_t j = i * i; j <= limit; j += 2 * i)
-                    comp[j / 2] = 1;
-        std::vector<uint32_t> pr, pairs;
-        for (uint64_t v = 5; v <= limit; v += 2)
-            if (!comp[v / 2]) {
-                pr.push_back((uint32_t)v);
-                pairs.push_back((uint32_t)v);
-                pairs.push_back(0u);
+        if (psieve)  // grow by at least a quarter, so rising limits re-sieve rarely
+            limit = std::max(limit, std::min<uint64_t>(psieve + psieve / 4, 1ull << 32));
+        const uint64_t root = isqrt_host(limit);
+        std::vector<uint8_t> bc(root / 2 + 1, 0);  // bc[i] <=> 2i+1 composite, 2i+1 <= root
+        std::vector<uint32_t> base;
+        for (uint64_t i = 3; i <= root; i += 2)
+            if (!bc[i / 2]) {
+                base.push_back((uint32_t)i);
+                for (uint64_t j = i * i; j <= root; j += 2 * i)
+                    bc[j / 2] = 1;
             }
+        std::vector<uint32_t> pr;
+        pr.reserve((size_t)(1.1 * (double)limit / std::max(1.0, std::log((double)limit))) + 16);
+        constexpr uint64_t SPAN = 1ull << 19;  // odd numbers per segment
+        std::vector<uint8_t> comp(SPAN);
+        for (uint64_t lo = 1; lo <= limit; lo += 2 * SPAN) {  // odd v in [lo, lo + 2 SPAN)
+            std::fill(comp.begin(), comp.end(), 0);
+            const uint64_t hi = std::min(lo + 2 * SPAN - 1, limit);
+            for (uint32_t q : base) {
+                const uint64_t qq = (uint64_t)q * q;
+                if (qq > hi)
+                    break;
+                uint64_t f = std::max(qq, (lo + q - 1) / q * q);
+                if (f % 2 == 0)
+                    f += q;
+                for (uint64_t v = f; v <= hi; v += 2 * q)
+                    comp[(v - lo) / 2] = 1;
+            }
+            for (uint64_t v = std::max<uint64_t>(lo, 5); v <= hi; v += 2)
+                if (!comp[(v - lo) / 2])
+                    pr.push_back((uint32_t)v);
+        }
         const size_t np = pr.size();
+        std::vector<uint32_t> pairs(2 * np, 0u);
+        for (size_t i = 0; i < np; ++i)
+            pairs[2 * i] = pr[i];
         RCCHK(ensure(pres, np * 8));
         RCCHK(ensure(res2, np * 8));
         HIPCHK(hipMemcpy(pres.p, pairs.data(), np * 8, hipMemcpyHostToDevice));
@@ -314,11 +338,16 @@ struct SieveState {
         b.n_sieve = count_primes_upto(std::max<uint64_t>(ceil_sqrt_host(y2), SMALL_P));
         const uint32_t n_mid = count_primes_upto(SEG);
         b.n_bucket = (b.n_sieve > n_mid && b.n_sieve - n_mid >= bucket_min) ? n_mid : b.n_sieve;
+        b.n_lane = std::max(b.n_bucket, count_primes_upto((uint64_t)b.nseg * SEG / 64));
+        b.n_lane = std::min(b.n_lane, b.n_sieve);
         b.bk_cnt = bk_cnt.as<uint32_t>();
         b.bk_start = bk_start.as<uint32_t>();
         b.bk_buf = bk_buf.as<uint32_t>();
         b.n_sq = count_primes_upto(isqrt_host(y2));
         b.n_sq_lds = std::min(count_primes_upto(SQ_LDS_P), b.n_sq);
+        b.n_sq_lane = std::min(std::max(count_primes_upto(isqrt_host((uint64_t)b.nseg * SEG / 64)),
+                                        b.n_sq_lds),
+                               b.n_sq);
         b.pat_off = (uint32_t)(y1 % PAT);
         b.pres = pres.as<uint2>();
         b.res2 = res2.as<uint64_t>();
@@ -352,9 +381,11 @@ struct SieveState {
         p.nseg = b.nseg;
         p.n_sq = b.n_sq;
         p.n_sq_lds = b.n_sq_lds;
+        p.n_sq_lane = b.n_sq_lane;
         p.pat_off = b.pat_off;
         p.n_sieve = b.n_sieve;
         p.n_bucket = b.n_bucket;
+        p.n_lane = b.n_lane;
         return p;
     }
 
@@ -365,11 +396,16 @@ struct SieveState {
         BlockArgs b = make_block(0, B - 1);
         b.nseg = (uint32_t)(B / SEG);
         b.n_sq_lds = 0;
+        // grid sizes only: the wave kernel covers every n_sq_lane a block of
+        // length <= B can have, the lane kernel every prime of the table
+        b.n_sq_lane = count_primes_upto(isqrt_host(B / 64));
+        b.n_sq = (uint32_t)h_primes.size() + b.n_sq_lane;
         b.n_sq = (uint32_t)h_primes.size();
         b.n_sieve = (uint32_t)h_primes.size();
         // capture the bucket kernels whenever some block may use them
         const uint32_t n_mid = count_primes_upto(SEG);
         b.n_bucket = (b.n_sieve > n_mid && b.n_sieve - n_mid >= bucket_min) ? n_mid : b.n_sieve;
+        b.n_lane = std::min(std::max(b.n_bucket, count_primes_upto(B / 64)), b.n_sieve);
         return b;
     }
 
@@ -735,6 +771,7 @@ struct Ctx {
     uint64_t serve_short_blocks = 4;       // requests needing at most this many blocks
     SieveState ss;
     Batch batch;
+    DevBuf iv_part, iv_small, iv_vals;  // interval sweep: partial extremes, scalars, values
     // last query (for byproducts): per caller index, L and first global index
     std::vector<uint64_t> last_L, last_g0;
     std::vector<int64_t> last_j;  // index in the batch, -1 for n = 0
@@ -746,6 +783,9 @@ struct Ctx {
 
 Ctx g;
 
+// largest interval end: the last block's end and sqrt(b) stay in range
+constexpr uint64_t INTERVAL_NMAX = ~0ull - (1ull << 32) + 1;
+
 void serve_stop();
 
 void free_all()
@@ -753,6 +793,9 @@ void free_all()
     serve_stop();
     g.ss.release();
     g.batch.release();
+    g.iv_part.release();
+    g.iv_small.release();
+    g.iv_vals.release();
     for (hipEvent_t e : g.events)
         (void)hipEventDestroy(e);
     g.events.clear();
@@ -1335,6 +1378,106 @@ int mertens_byproducts(size_t i, int64_t *buf, size_t cap, size_t *len)
                               hipMemcpyDeviceToHost, g.stream));
     }
     HIPCHK(hipStreamSynchronize(g.stream));
+    return 0;
+}
+
+int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, uint64_t *n_ext,
+                     int64_t *m_ext, int64_t *values, size_t cap)
+{
+    if (a == 0 || b < a || b > INTERVAL_NMAX) {
+        set_error_text("interval needs 1 <= a <= b <= 2^64 - 2^32");
+        return MERTENS_EINVAL;
+    }
+    const uint64_t len = b - a + 1;  // no wrap: b - a < 2^64 - 1
+    if (values && (len > (1ull << 28) || cap < len)) {
+        set_error_text("values needs cap >= b - a + 1 and b - a + 1 <= 2^28");
+        return MERTENS_EINVAL;
+    }
+    if (!g.ready) {
+        set_error_text("mertens_init has not been called");
+        return MERTENS_ENODEV;
+    }
+    int64_t ma = 0;
+    if (m_a) {
+        ma = *m_a;
+    } else {
+        std::vector<int64_t> r;
+        g.last_valid = false;  // the query replaces the last query's arrays
+        RCCHK(run_query({a}, r));
+        ma = r[0];
+    }
+    hipStream_t s = g.stream;
+    const uint64_t start = a - a % SEG;
+    RCCHK(g.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(b), 1024)));
+    RCCHK(g.ss.ensure_pattern());
+    const uint64_t B =
+        g.block_req ? g.block_req : std::min<uint64_t>((b - start) / SEG * SEG + SEG, 1ull << 30);
+    RCCHK(g.ss.ensure_blocks(B, 1));
+    RCCHK(ensure(g.iv_part, (size_t)IV_WGS * 32));
+    RCCHK(ensure(g.iv_small, 64));  // off at [0], results at [1..5]
+    if (values)
+        RCCHK(ensure(g.iv_vals, len * 8));
+    const uint64_t nblocks = (b - start) / B + 1;
+    if (!event_at(3 * nblocks + 2)) {
+        set_error_text("hipEventCreate failed");
+        return MERTENS_EIO;
+    }
+    int64_t *off = g.iv_small.as<int64_t>(), *res = off + 1;
+    size_t ev = 0;
+    HIPCHK(hipEventRecord(g.events[ev++], s));
+    RCCHK(g.ss.reset_carry(s));
+    HIPCHK(launch_zero_u64(g.iv_part.as<uint64_t>(), (size_t)IV_WGS * 4, s));
+    std::vector<size_t> marks;
+    for (uint64_t y1 = start;; y1 += B) {
+        const uint64_t y2 = b - y1 < B ? b : y1 + B - 1;
+        const BlockArgs blk = g.ss.make_block(y1, y2);
+        marks.push_back(ev);
+        HIPCHK(hipEventRecord(g.events[ev], s));
+        RCCHK(g.ss.sieve(blk, s, nullptr));
+        HIPCHK(hipEventRecord(g.events[ev + 1], s));
+        if (y1 == start)
+            HIPCHK(launch_interval_base(blk, a, ma, off, s));
+        const uint64_t lo = std::max(y1, a);
+        HIPCHK(launch_interval_extreme(blk, lo, y2, off, g.iv_part.as<uint64_t>(), s));
+        if (values)
+            HIPCHK(launch_interval_values(blk, lo, y2 - lo + 1, off,
+                                          g.iv_vals.as<int64_t>() + (lo - a), s));
+        if (y2 == b)
+            HIPCHK(launch_interval_final(blk, g.iv_part.as<uint64_t>(), b, off, res, s));
+        HIPCHK(hipEventRecord(g.events[ev + 2], s));
+        ev += 3;
+        if (y2 == b)
+            break;
+    }
+    HIPCHK(hipEventRecord(g.events[ev], s));
+    int64_t h[5];
+    HIPCHK(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (values)
+        HIPCHK(hipMemcpy(values, g.iv_vals.p, len * 8, hipMemcpyDeviceToHost));
+    if (m_b)
+        *m_b = h[4];
+    if (n_ext) {
+        n_ext[0] = (uint64_t)h[0];
+        n_ext[1] = (uint64_t)h[2];
+    }
+    if (m_ext) {
+        m_ext[0] = h[1];
+        m_ext[1] = h[3];
+    }
+    double t_sieve = 0, t_red = 0;
+    for (size_t m : marks) {
+        t_sieve += elapsed(m, m + 1);
+        t_red += elapsed(m + 1, m + 2);
+    }
+    for (double &v : g.stats)
+        v = 0;
+    g.stats[0] = (double)(b - start + 1);
+    g.stats[1] = (double)nblocks;
+    g.stats[6] = t_sieve;
+    g.stats[9] = t_red;
+    g.stats[11] = elapsed(0, ev);
+    g.stats[13] = (double)nblocks;
     return 0;
 }
 

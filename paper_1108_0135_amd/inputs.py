@@ -52,3 +52,15 @@ def poisson_trace(seed: int, rate: float, count: int, lo: float = 1e10, hi: floa
     gaps = rng.exponential(1.0 / rate, count)
     times = np.cumsum(gaps) - gaps[0]
     return times, log_uniform(seed + 1, count, lo, hi)
+
+
+def interval_around(seed: int, lo: int, hi: int, before: int, after: int):
+    """(a, b) = (c - before, c + after) with c uniform in [lo, hi]."""
+    rng = np.random.default_rng(seed)
+    c = int(rng.integers(lo, hi, endpoint=True, dtype=np.uint64))
+    return c - before, c + after
+
+
+def extreme_window(before: int = 2**20 + 12345, after: int = 2**20 + 777):
+    """(a, b) around the Section 6 extreme (the localization workload)."""
+    return EXTREME_N - before, EXTREME_N + after

@@ -40,6 +40,8 @@ _sig = {
     "mertens_last_error": ([], ctypes.c_char_p),
     "mertens_submit": ([_u64, _P(_u64)], ctypes.c_int),
     "mertens_poll": ([_u64, _P(_i64), _P(ctypes.c_double)], ctypes.c_int),
+    "mertens_interval": ([_u64, _u64, _P(_i64), _P(_i64), _P(_u64), _P(_i64), _P(_i64), _sz],
+                         ctypes.c_int),
     "mertens_debug_div": ([_P(_u64), _P(_u64), _sz, _P(_u64), ctypes.c_int], ctypes.c_int),
     "mertens_debug_mu": ([_u64, _sz, _P(ctypes.c_int8), _P(_i64)], ctypes.c_int),
 }
@@ -122,6 +124,24 @@ def poll(ticket: int):
         return None
     _check(rc, "mertens_poll")
     return out.value, lat.value
+
+
+def interval(a: int, b: int, m_a: int | None = None, values: bool = False) -> dict:
+    """M over [a, b] from M(a) (computed first when not given): M(b), the n with
+    the smallest and largest M(n)/sqrt(n) and M there, and, if asked, every M(n)."""
+    ma = _i64(0 if m_a is None else int(m_a))
+    mb = _i64(0)
+    n_ext = (_u64 * 2)()
+    m_ext = (_i64 * 2)()
+    vals = np.zeros(b - a + 1 if values else 1, dtype=np.int64)
+    _check(_lib.mertens_interval(a, b, None if m_a is None else ctypes.byref(ma), ctypes.byref(mb),
+                                 n_ext, m_ext, _i64p(vals) if values else None,
+                                 vals.size if values else 0), "mertens_interval")
+    out = {"m_b": int(mb.value), "n_min": int(n_ext[0]), "m_min": int(m_ext[0]),
+           "n_max": int(n_ext[1]), "m_max": int(m_ext[1])}
+    if values:
+        out["values"] = vals
+    return out
 
 
 def set_param(key: str, value: float) -> None:

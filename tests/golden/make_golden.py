@@ -3,6 +3,8 @@
 Calls only the CPU oracle (``oracle/``) on the seeded inputs of
 ``paper_1108_0135_amd.inputs``; never the GPU path.  Re-run after any change
 to the oracle's arithmetic:  python tests/golden/make_golden.py
+(``--only-intervals tests/golden/golden.json`` refreshes just the interval
+entries of an existing file.)
 """
 from __future__ import annotations
 
@@ -21,8 +23,41 @@ import oracle  # noqa: E402
 from paper_1108_0135_amd import inputs  # noqa: E402
 
 
+def interval_cases(out: dict) -> None:
+    """Section 6 interval sweeps (O3 on top of O2 or of the paper's value)."""
+    # a ragged interval of 3 * 2^20 + 12346 values at a height of ~1e12 (seed 3)
+    a, b = inputs.interval_around(3, 10**12, 2 * 10**12, 0, 3 * 2**20 + 12345)
+    o2 = oracle.IdentityOracle(10**8)
+    m_a = o2.query(a)[0]
+    r = oracle.interval(a, b, m_a)
+    assert r["m_b"] == o2.query(b)[0]  # the two tiers agree at the far end
+    out["interval1e12"] = {"seed": 3, "a": a, "b": b, "m_a": m_a, **r}
+
+    # the neighbourhood of the Section 6 extreme: M(a) from the printed
+    # M(EXTREME_N) minus the oracle's mu over (a, EXTREME_N], then O3
+    a, b = inputs.extreme_window()
+    mu = oracle.mu_range(a, b).astype(np.int64)  # mu[i] = mu(a + i)
+    m_a = inputs.EXTREME_M - int(mu[1:inputs.EXTREME_N - a + 1].sum())
+    r = oracle.interval(a, b, m_a)
+    assert (r["n_min"], r["m_min"]) == (inputs.EXTREME_N, inputs.EXTREME_M)
+    rng = np.random.default_rng(8)
+    idx = sorted(int(i) for i in rng.choice(b - a + 1, 64, replace=False))
+    run = m_a + np.cumsum(mu[1:])  # run[i - 1] = M(a + i)
+    samples = {str(a + i): (m_a if i == 0 else int(run[i - 1])) for i in idx}
+    out["extreme_window"] = {"a": a, "b": b, "m_a": m_a, **r, "samples": samples}
+
+
 def main() -> None:
     t0 = time.time()
+    if len(sys.argv) > 2 and sys.argv[1] == "--only-intervals":
+        # refresh only the interval entries of an existing file
+        path = sys.argv[2]
+        out = json.load(open(path))
+        interval_cases(out)
+        with open(path, "w") as f:
+            json.dump(out, f)
+        print(f"updated {path} in {time.time() - t0:.1f} s")
+        return
     out = {"generator": "tests/golden/make_golden.py (oracle only)"}
 
     # the brute-force-checkable set: 32 n uniform in [2, 1e9], seed 0 (O1 sweep)
@@ -58,6 +93,8 @@ def main() -> None:
     mu = oracle.mu_range(nd[0] + 1, nd[-1])
     diffs = [int(mu[nd[i] - nd[0]:nd[i + 1] - nd[0]].astype(np.int64).sum()) for i in range(7)]
     out["window1e19_diffs"] = {"seed": 0, "n": nd, "diffs": diffs}
+
+    interval_cases(out)
 
     path = os.path.join(HERE, "golden.json")
     with open(path, "w") as f:

@@ -44,6 +44,13 @@ def test_bad_arguments_without_gpu():
                      (b"kbal", 2.5), (b"klchunk", 256.0), (b"graph", 0.5),
                      (b"bucket_min", 0.0)):
         assert lib.mertens_set_param(key, bad) == mt.EINVAL, key
+    # interval: a >= 1, a <= b <= 2^64 - 2^32, values need room and at most 2^28 of them
+    vals = np.zeros(4, dtype=np.int64)
+    for a, b, cap in ((0, 5, 0), (9, 8, 0), (1, 2**64 - 2**32 + 1, 0), (1, 10, 4),
+                      (10**12, 10**12 + 2**28, 2**29)):
+        use = cap > 0
+        assert lib.mertens_interval(a, b, None, None, None, None,
+                                    mt._i64p(vals) if use else None, cap) == mt.EINVAL, (a, b)
     # divisor outside [1, 2^32)
     n = np.array([5], dtype=np.uint64)
     for bad in (0, 1 << 32):
@@ -62,6 +69,7 @@ def test_no_device_here_or_initialised():
     n = np.array([10], dtype=np.uint64)
     out = np.zeros(1, dtype=np.int64)
     assert lib.mertens_query(mt._u64p(n), 1, mt._i64p(out)) == mt.ENODEV
+    assert lib.mertens_interval(5, 10, None, None, None, None, None, 0) == mt.ENODEV
 
 
 def _div_cases(rng):

@@ -275,3 +275,62 @@ def test_batched_256_full_size_sampled(mt):
     rng = np.random.default_rng(7)
     for i in sorted(rng.choice(256, 12, replace=False)):
         assert int(mt.query([ns[i]])[0]) == got[i], (i, ns[i])
+
+
+# ------------------------------------------------------------------ interval sweeps
+
+def _interval_oracle(a, b, m_a):
+    """Every M(n), n in [a, b], from M(a) and the oracle's mu, plus O3's extremes."""
+    mu = oracle.mu_range(a + 1, b).astype(np.int64) if b > a else np.zeros(0, np.int64)
+    vals = np.concatenate([[m_a], m_a + np.cumsum(mu)])
+    return vals, oracle.interval(a, b, m_a)
+
+
+@pytest.mark.parametrize("a,b,block", [
+    (1, 1, 0), (1, 10, 0), (2, 39, 0), (93, 101, 0),      # ties at ratio 0 keep the smaller n
+    (1, (1 << 21) + 5, 1 << 17),                             # 17 blocks from y = 0
+    (10**9 - 70_000, 10**9 + 3 * 2**17 + 11, 1 << 17),       # unaligned start, ragged end
+    (2**40 - 1000, 2**40 + 10**6, 1 << 18),
+    (10**12 + 7, 10**12 + 7, 0),                             # a single point
+])
+def test_interval_small_vs_oracle(mt, a, b, block):
+    _reinit(mt, block=block)
+    m_a = oracle.mertens(a)
+    vals, ref = _interval_oracle(a, b, m_a)
+    got = mt.interval(a, b, m_a=m_a, values=True)
+    assert np.array_equal(got["values"], vals)
+    for k in ("m_b", "n_min", "m_min", "n_max", "m_max"):
+        assert got[k] == ref[k], k
+
+
+def test_interval1e12_golden_and_block_invariance(mt):
+    # 3 * 2^20 + 12346 values at ~1.5e12; M(a) from the library's own query
+    g = GOLDEN["interval1e12"]
+    assert inputs.interval_around(g["seed"], 10**12, 2 * 10**12, 0, 3 * 2**20 + 12345) == \
+        (g["a"], g["b"])
+    keys = ("m_b", "n_min", "m_min", "n_max", "m_max")
+    first = None
+    for block in (1 << 17, 1 << 20, 0):
+        _reinit(mt, block=block)
+        got = mt.interval(g["a"], g["b"], m_a=None if block == 0 else g["m_a"], values=True)
+        assert {k: got[k] for k in keys} == {k: g[k] for k in keys}, block
+        assert int(got["values"][0]) == g["m_a"]
+        if first is None:
+            first = got["values"]
+        assert np.array_equal(got["values"], first), block
+
+
+def test_interval_section6_extreme_window(mt):
+    # Section 6: M(a) by a query at ~1.16e19, the sieve over 2^21 values with
+    # primes up to 3.4e9 (bucketed), and the smallest M(n)/sqrt(n) in the
+    # window at n = 11609864264058592345 with M = -1,995,900,927
+    g = GOLDEN["extreme_window"]
+    assert inputs.extreme_window() == (g["a"], g["b"])
+    _reinit(mt)
+    got = mt.interval(g["a"], g["b"], values=True)
+    assert (got["n_min"], got["m_min"]) == (inputs.EXTREME_N, inputs.EXTREME_M)
+    for k in ("m_b", "n_max", "m_max"):
+        assert got[k] == g[k], k
+    assert int(got["values"][0]) == g["m_a"]
+    for n, m in g["samples"].items():
+        assert int(got["values"][int(n) - g["a"]]) == m, n
