@@ -15,6 +15,8 @@ Other workloads (``--workload``), reported separately:
   serving  Poisson arrivals (``--rate`` q/s, ``--count`` queries, n
            log-uniform in [1e10, 1e18]) through mertens_submit/poll vs. a
            one-at-a-time FIFO server; p50/p99 latency and queries/s
+  interval Section 6 localization: M(n) for every n of a 2^35-wide interval
+           from the printed extreme on, and the extremes of M(n)/sqrt(n)
 """
 from __future__ import annotations
 
@@ -54,10 +56,10 @@ def kernel_source_sha256() -> str:
     return h.hexdigest()
 
 
-def traffic_per_launch(kernel: str):
+def traffic_per_launch(kernel: str, workload: str = "n1e16"):
     """HBM bytes per launch from the committed counter summary, or None if the
     kernels changed since the counters were taken."""
-    path = os.path.join(ROOT, "profiles", f"{kernel}_n1e16_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -271,6 +273,85 @@ def workload_serving(args, mt) -> dict:
                            "p99_s": p(fifo_lat, 99)}}
 
 
+IV_WIDTH = 2**35  # interval workload: [EXTREME_N, EXTREME_N + 2^35]
+
+
+def cpu_baseline_interval() -> dict:
+    """The oracle's interval tier (O3) on a 2^21-wide piece of the same interval."""
+    import oracle
+    from paper_1108_0135_amd import inputs
+    oracle.build()
+    w = 2**21
+    t0 = time.perf_counter()
+    r = oracle.interval(inputs.EXTREME_N, inputs.EXTREME_N + w, inputs.EXTREME_M)
+    dt = time.perf_counter() - t0
+    if (r["n_min"], r["m_min"]) != (inputs.EXTREME_N, inputs.EXTREME_M):
+        raise RuntimeError("oracle interval missed the Section 6 extreme")
+    return {"value": (w + 1) / dt, "unit": "y/s", "cores": 1, "kind": "oracle",
+            "sample": f"O3 over [{inputs.EXTREME_N}, +2^21] (single thread, {dt:.1f} s, most of "
+                      f"it building its prime table up to 3.4e9)"}
+
+
+def workload_interval(args, mt) -> dict:
+    """Section 6 localization: every M(n) over a 2^35-wide interval starting at the
+    printed extreme, from its printed value, and the extremes of M(n)/sqrt(n)."""
+    import torch
+    from paper_1108_0135_amd import inputs
+    a, b = inputs.EXTREME_N, inputs.EXTREME_N + IV_WIDTH
+    mt.init(0, 0)
+
+    def step():
+        r = mt.interval(a, b, m_a=inputs.EXTREME_M)
+        if (r["n_min"], r["m_min"]) != (inputs.EXTREME_N, inputs.EXTREME_M):
+            raise RuntimeError(f"interval minimum moved: {r}")
+        return r, mt.stats()
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = [step()[1] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms_step = 1000.0 * (time.perf_counter() - t0) / args.steps
+    st = sts[-1]
+    avg = lambda k: sum(x[k] for x in sts) / len(sts)
+    # per-kernel launch times (HIP events on the library stream) and
+    # algorithmic bytes: the fill pass writes one 4-byte entry per multiple of
+    # a bucketed prime and reads each bucketed prime's 8-byte {p, residue};
+    # the regrouping pass reads and writes every entry once; the sieve reads
+    # its entries and writes 0.5 byte of records per y
+    nb = st["blocks"]
+    ent = st["bucket_entries"] / nb
+    kern = {
+        "k_bucket_regroup": (st["ms_bucket_regroup"] / nb, 8 * ent),
+        "k_prime_buckets_fill": (st["ms_bucket_fill"] / nb, 4 * ent + 8 * st["bucket_prime_visits"] / nb),
+        "k_sieve": (st["ms_sieve"] / nb, 4 * ent + 0.5 * st["sieved_y"] / nb),
+    }
+    name = max(kern, key=lambda k: kern[k][0])
+    ms_l, bytes_l = kern[name]
+    gbs = bytes_l / (ms_l * 1e-3) / 1e9
+    roof = {"kernel": name, "bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": gbs / HBM_PEAK_GBS, "traffic": traffic_per_launch(name, "interval1e19"),
+            "algorithmic_bytes_per_launch": bytes_l, "avg_launch_ms": ms_l, "launches": nb,
+            "entries_per_launch": ent,
+            "traffic_unit": ("bytes per launch between L2 and memory (rocprofv3 FETCH_SIZE x2 + "
+                             "WRITE_SIZE x1, calibrated on a plain copy)"),
+            "per_kernel_ms": {k: v[0] for k, v in kern.items()}}
+    return {
+        "metric": "values of M(n) per second over an interval (Section 6 localization)",
+        "value": (b - a + 1) / (ms_step * 1e-3), "unit": "y/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
+        "data": "synthetic",
+        "config": {"workload": f"interval [11609864264058592345, +2^35] from the printed M there, "
+                               f"primes to 3.4e9 (bucketed), y-blocks of 2^30",
+                   "blocks": st["blocks"], "parallelism": "1 GPU"},
+        "kernel_ms": {k: avg(k) for k in ("ms_prep", "ms_sieve", "ms_update", "ms_bucket_fill",
+                                          "ms_bucket_regroup", "ms_total")},
+        "roofline": roof,
+    }
+
+
 def workload_copy(args, mt) -> dict:
     """A plain device copy of known size (calibrates HBM byte counters)."""
     import torch
@@ -293,7 +374,7 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["default", "batched", "serving", "copy"],
+    ap.add_argument("--workload", choices=["default", "batched", "serving", "interval", "copy"],
                     default="default")
     ap.add_argument("--rate", type=float, default=10.0)
     ap.add_argument("--count", type=int, default=48)
@@ -318,6 +399,10 @@ def main() -> int:
                 line["cpu_baseline"] = cpu_baseline()
         elif args.workload == "batched":
             line = workload_batched(args, mt)
+        elif args.workload == "interval":
+            line = workload_interval(args, mt)
+            if not args.no_cpu_baseline:
+                line["cpu_baseline"] = cpu_baseline_interval()
         elif args.workload == "copy":
             line = workload_copy(args, mt)
         else:

@@ -166,7 +166,7 @@ int mertens_set_stream(void *hip_stream);
 int mertens_set_param(const char *key, double value);
 
 /*
- * mertens_stats -- counters of the last mertens_query, for benchmarking.
+ * mertens_stats -- counters of the last mertens_query or mertens_interval (benchmarking).
  * Writes up to cap doubles into vals in this order (returns how many):
  *   0 sieved y (Ymax+1)   1 blocks         2 u used        3 sum of L
  *   4 sum over x of Y (run-length range)  5 sum over x of explicit k terms
@@ -175,6 +175,8 @@ int mertens_set_param(const char *key, double value);
  *  10 ms finalize         11 ms total device time          12 update launches
  *  13 sieve launches      14 run-length quotients taken (mu(y) != 0, y <= Y)
  *  15 explicit k quotients taken (= M(y) gathers)
+ *  16 bucket entries listed    17 ms bucket fill pass    18 bucketed prime visits
+ *  19 ms bucket regrouping pass   (16-19: mertens_interval only, 0 after a query)
  * Kernel times are HIP-event intervals on the library's stream.
  */
 int mertens_stats(double *vals, int cap);
@@ -208,8 +210,11 @@ const char *mertens_last_error(void);
  * The sweep sieves mu over [a - (a mod 2^17), b] in blocks (device primes up
  * to ceil(sqrt(b)), the ones above 2^17 through per-segment buckets), runs
  * the M(y) prefix from zero, and shifts it by M(a) minus the prefix at a.
- * mertens_stats afterwards: sieved_y, blocks, ms_sieve (sieve and buckets),
- * ms_update (the interval reductions), ms_total; the other slots 0.
+ * mertens_stats afterwards: sieved_y, blocks, ms_sieve (the sieve kernel
+ * with its fused prefix), ms_prep (block set-up, square and prime buckets),
+ * ms_update (the interval reductions), ms_total, sieve_launches and slots
+ * 16-19 (bucket entries, fill-pass ms, bucketed prime visits, regrouping
+ * ms); others 0.
  * Returns 0, MERTENS_EINVAL, MERTENS_ENOMEM, MERTENS_ENODEV, MERTENS_EIO.
  */
 int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, uint64_t *n_ext,

@@ -35,6 +35,12 @@ constexpr uint32_t SQ_BUCKET = 64;
 #endif
 constexpr uint32_t BK_WGS = MERTENS_BK_WGS, BK_THREADS = 1024;
 constexpr uint32_t MAX_SEGS = (1u << 31) / SEG;  // segments of the longest block
+// The fill pass lists hits per group of BK_GROUP_SEGS segments (2^24 y)
+// first, and a second pass spreads each group over its segments: both
+// write into few runs at a time, which the L2 turns into whole-line writes.
+constexpr uint32_t BK_GROUP_SEGS = 128, BK_GROUP_SHIFT = 24;
+static_assert(BK_GROUP_SEGS * SEG == (1u << BK_GROUP_SHIFT), "group size");
+static_assert(MAX_SEGS / BK_GROUP_SEGS <= MAX_SEGS, "group counters fit the LDS array");
 // Interval sweep: workgroups of the extreme reduction (each keeps its own
 // running candidates across the blocks of one interval).
 constexpr uint32_t IV_WGS = 2048, IV_THREADS = 256;
@@ -91,6 +97,8 @@ struct BlockArgs {
     uint32_t *bk_cnt;
     uint32_t *bk_start;
     uint32_t *bk_buf;
+    uint32_t *bk_stage;       // fill-pass entries per (group, workgroup) before regrouping
+    uint64_t *bk_total;       // running count of bucket entries over blocks
     int64_t *carry;           // M(y1 - 1), advanced by the block's last segment
 };
 
@@ -140,7 +148,10 @@ hipError_t launch_plan(const QueryArgs &q, hipStream_t s);
 hipError_t launch_block_setup(const BlockArgs &b, hipStream_t s);
 hipError_t launch_square_buckets(const BlockArgs &b, hipStream_t s);
 // multiples of the primes above SEG, sorted into per-segment buckets
-hipError_t launch_prime_buckets(const BlockArgs &b, hipStream_t s);
+// (events, if given, are recorded before the fill pass, between it and the
+// regrouping pass, and after that)
+hipError_t launch_prime_buckets(const BlockArgs &b, hipStream_t s, hipEvent_t fill0 = nullptr,
+                                hipEvent_t fill1 = nullptr, hipEvent_t fill2 = nullptr);
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s);
 hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
 hipError_t launch_scan_items(const QueryArgs &q, hipStream_t s);

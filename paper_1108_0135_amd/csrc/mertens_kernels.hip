@@ -418,6 +418,22 @@ __device__ inline uint32_t bucket_entry(uint64_t o, uint32_t lp)
     return (uint32_t)(o % SEG) | (lp << 17);
 }
 
+// Fill-pass entry in a group: offset in the group (24 bits) | log << 24.
+__device__ inline uint32_t group_entry(uint64_t o, uint32_t lp)
+{
+    return (uint32_t)(o & ((1u << BK_GROUP_SHIFT) - 1)) | (lp << BK_GROUP_SHIFT);
+}
+
+// The first staged entry of workgroup w in group g is the group's first
+// entry, bk_start[g * BK_GROUP_SEGS], plus the counts of workgroups before w
+// over the group's segments (bk_cnt holds those per segment once
+// k_bucket_columns has run); both kernels below add them up with LDS atomics.
+
+// Count pass (FILL = false): the workgroup's hits per segment, into bk_cnt.
+// Fill pass: every hit into the workgroup's run of its 2^24-y group in
+// bk_stage, in the group-major layout k_bucket_regroup reads (so each
+// workgroup appends to at most MAX_GROUPS runs at a time, which the L2
+// gathers into whole lines).
 template <bool FILL>
 __global__ __launch_bounds__(BK_THREADS) void k_prime_buckets(BlockArgs b_in)
 {
@@ -427,8 +443,17 @@ __global__ __launch_bounds__(BK_THREADS) void k_prime_buckets(BlockArgs b_in)
         return;
     const uint32_t tid = threadIdx.x, w = blockIdx.x;
     uint32_t *mine = b.bk_cnt + (size_t)w * b.nseg;
-    for (uint32_t sg = tid; sg < b.nseg; sg += BK_THREADS)
-        cnt[sg] = FILL ? b.bk_start[sg] + mine[sg] : 0u;
+    if (FILL) {
+        const uint32_t ng = (b.nseg + BK_GROUP_SEGS - 1) / BK_GROUP_SEGS;
+        for (uint32_t g = tid; g < ng; g += BK_THREADS)
+            cnt[g] = b.bk_start[g * BK_GROUP_SEGS];
+        __syncthreads();
+        for (uint32_t sg = tid; sg < b.nseg; sg += BK_THREADS)
+            atomicAdd(&cnt[sg / BK_GROUP_SEGS], mine[sg]);
+    } else {
+        for (uint32_t sg = tid; sg < b.nseg; sg += BK_THREADS)
+            cnt[sg] = 0u;
+    }
     __syncthreads();
     const uint64_t span = (uint64_t)b.nseg * SEG;
     constexpr uint32_t WAVES = BK_THREADS / 64;
@@ -441,8 +466,8 @@ __global__ __launch_bounds__(BK_THREADS) void k_prime_buckets(BlockArgs b_in)
         const uint32_t lp = log_prime(e.x);
         for (uint64_t o = (e.y ? p - e.y : 0) + lane * p; o < span; o += 64 * p) {
             if (FILL) {
-                const uint32_t k = atomicAdd(&cnt[o / SEG], 1u);
-                b.bk_buf[k] = bucket_entry(o, lp);
+                const uint32_t k = atomicAdd(&cnt[o >> BK_GROUP_SHIFT], 1u);
+                b.bk_stage[k] = group_entry(o, lp);
             } else {
                 atomicAdd(&cnt[o / SEG], 1u);
             }
@@ -456,17 +481,104 @@ __global__ __launch_bounds__(BK_THREADS) void k_prime_buckets(BlockArgs b_in)
         const uint32_t lp = log_prime(e.x);
         for (uint64_t o = e.y ? p - e.y : 0; o < span; o += p) {
             if (FILL) {
-                const uint32_t k = atomicAdd(&cnt[o / SEG], 1u);
-                b.bk_buf[k] = bucket_entry(o, lp);
+                const uint32_t k = atomicAdd(&cnt[o >> BK_GROUP_SHIFT], 1u);
+                b.bk_stage[k] = group_entry(o, lp);
             } else {
                 atomicAdd(&cnt[o / SEG], 1u);
             }
         }
     }
-    __syncthreads();
-    if (!FILL)
+    if (!FILL) {
+        __syncthreads();
         for (uint32_t sg = tid; sg < b.nseg; sg += BK_THREADS)
             mine[sg] = cnt[sg];
+    }
+}
+
+// Second level: workgroup (w, g) moves fill-pass workgroup w's run of group
+// g from bk_stage to the per-segment lists of bk_buf (segment sg's entries
+// of w start at bk_start[sg] + bk_cnt[w][sg]).  It takes the run in chunks
+// of RG_CHUNK entries, sorts each chunk by segment in LDS (count with ranks,
+// scan, scatter) and writes it out in that order, so consecutive threads
+// write consecutive words of one segment's list.
+constexpr uint32_t RG_THREADS = 512, RG_CHUNK = 8192, RG_PER = RG_CHUNK / RG_THREADS;
+
+__global__ __launch_bounds__(RG_THREADS) void k_bucket_regroup(BlockArgs b_in)
+{
+    const BlockArgs b = load_block(b_in);
+    __shared__ uint32_t pos[BK_GROUP_SEGS];  // next bk_buf index per segment
+    __shared__ uint32_t cnt[BK_GROUP_SEGS];  // entries per segment in the chunk
+    __shared__ uint32_t off[BK_GROUP_SEGS];  // their first index in `sorted`
+    __shared__ uint32_t range[2];
+    __shared__ uint32_t sorted[RG_CHUNK];
+    if (b.n_bucket >= b.n_sieve)
+        return;
+    const uint32_t ng = (b.nseg + BK_GROUP_SEGS - 1) / BK_GROUP_SEGS;
+    const uint32_t w = blockIdx.x % BK_WGS, g = blockIdx.x / BK_WGS;
+    if (g >= ng)
+        return;
+    const uint32_t tid = threadIdx.x, s0 = g * BK_GROUP_SEGS;
+    const uint32_t s1 = s0 + BK_GROUP_SEGS < b.nseg ? s0 + BK_GROUP_SEGS : b.nseg;
+    const bool last = w + 1 == BK_WGS;
+    constexpr uint32_t OMASK = (1u << BK_GROUP_SHIFT) - 1;
+    if (tid == 0) {
+        range[0] = b.bk_start[s0];
+        range[1] = last ? b.bk_start[s1] : b.bk_start[s0];
+    }
+    if (tid < BK_GROUP_SEGS)
+        pos[tid] = 0;
+    __syncthreads();
+    if (tid < BK_GROUP_SEGS && s0 + tid < s1) {
+        const uint32_t *pre = b.bk_cnt + (size_t)w * b.nseg + s0 + tid;
+        pos[tid] = b.bk_start[s0 + tid] + pre[0];
+        atomicAdd(&range[0], pre[0]);
+        if (!last)
+            atomicAdd(&range[1], pre[b.nseg]);
+    }
+    __syncthreads();
+    const uint32_t r0 = range[0], r1 = range[1];
+    for (uint32_t c0 = r0; c0 < r1; c0 += RG_CHUNK) {
+        const uint32_t n = r1 - c0 < RG_CHUNK ? r1 - c0 : RG_CHUNK;
+        if (tid < BK_GROUP_SEGS)
+            cnt[tid] = 0;
+        __syncthreads();
+        uint32_t val[RG_PER], rank[RG_PER];
+#pragma unroll
+        for (uint32_t k = 0; k < RG_PER; ++k) {
+            const uint32_t i = k * RG_THREADS + tid;
+            val[k] = i < n ? b.bk_stage[c0 + i] : 0u;
+            rank[k] = i < n ? atomicAdd(&cnt[(val[k] & OMASK) / SEG], 1u) : 0u;
+        }
+        __syncthreads();
+        if (tid < 64) {  // exclusive scan of the 128 counts, two per lane
+            const uint32_t a = cnt[2 * tid], c = cnt[2 * tid + 1];
+            uint32_t x = a + c;
+            for (int o = 1; o < 64; o <<= 1) {
+                const uint32_t t = __shfl_up(x, o, 64);
+                if (tid >= (uint32_t)o)
+                    x += t;
+            }
+            off[2 * tid] = x - a - c;
+            off[2 * tid + 1] = x - c;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t k = 0; k < RG_PER; ++k) {
+            const uint32_t i = k * RG_THREADS + tid;
+            if (i < n)
+                sorted[off[(val[k] & OMASK) / SEG] + rank[k]] = val[k];
+        }
+        __syncthreads();
+        for (uint32_t i = tid; i < n; i += RG_THREADS) {
+            const uint32_t v = sorted[i];
+            const uint32_t o = v & OMASK, sg = o / SEG;
+            b.bk_buf[pos[sg] + (i - off[sg])] = (o % SEG) | ((v >> BK_GROUP_SHIFT) << 17);
+        }
+        __syncthreads();
+        if (tid < BK_GROUP_SEGS)
+            pos[tid] += cnt[tid];
+        __syncthreads();
+    }
 }
 
 // Per segment (one thread each): exclusive prefix of the workgroups' counts
@@ -506,19 +618,32 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_bucket_starts(BlockArgs b_in)
             b.bk_start[sg] = (uint32_t)(base + (uint64_t)ex);
         base += (uint64_t)all;
     }
-    if (tid == 0)
+    if (tid == 0) {
         b.bk_start[b.nseg] = (uint32_t)base;
+        atomicAdd(reinterpret_cast<unsigned long long *>(b.bk_total), base);
+    }
 }
 
-hipError_t launch_prime_buckets(const BlockArgs &b, hipStream_t s)
+hipError_t launch_prime_buckets(const BlockArgs &b, hipStream_t s, hipEvent_t fill0,
+                                hipEvent_t fill1, hipEvent_t fill2)
 {
     if (b.n_bucket >= b.n_sieve)
         return hipSuccess;
     hipLaunchKernelGGL(k_prime_buckets<false>, dim3(BK_WGS), dim3(BK_THREADS), 0, s, b);
     hipLaunchKernelGGL(k_bucket_columns, dim3((b.nseg + 255) / 256), dim3(256), 0, s, b);
     hipLaunchKernelGGL(k_bucket_starts, dim3(1), dim3(SIEVE_THREADS), 0, s, b);
+    hipError_t e = hipSuccess;
+    if (fill0)
+        e = hipEventRecord(fill0, s);
     hipLaunchKernelGGL(k_prime_buckets<true>, dim3(BK_WGS), dim3(BK_THREADS), 0, s, b);
-    return hipGetLastError();
+    if (fill1 && e == hipSuccess)
+        e = hipEventRecord(fill1, s);
+    const uint32_t ng = (b.nseg + BK_GROUP_SEGS - 1) / BK_GROUP_SEGS;
+    hipLaunchKernelGGL(k_bucket_regroup, dim3(BK_WGS * ng), dim3(RG_THREADS), 0, s, b);
+    if (fill2 && e == hipSuccess)
+        e = hipEventRecord(fill2, s);
+    const hipError_t l = hipGetLastError();
+    return l != hipSuccess ? l : e;
 }
 
 // Look-back states of the fused scan.

@@ -181,7 +181,7 @@ struct SieveState {
     uint64_t psieve = 0;
     std::vector<uint32_t> h_primes;  // primes >= 5 up to psieve
     DevBuf pres, res2, pattern, words, seg_state, sq_cnt, sq_buf, bk_cnt, bk_start, bk_buf,
-        carry, bp_cur, bp_table, bp_index;
+        bk_stage, carry, bp_cur, bp_table, bp_index;
     uint32_t bucket_min = 1u << 20;  // bucket the primes above SEG when a block has this many
     long double bk_cap = 0;           // bucket entries a block of bk_cap_B can need
     uint64_t bk_cap_B = 0, bk_cap_np = 0;
@@ -190,7 +190,8 @@ struct SieveState {
     void release()
     {
         DevBuf *bufs[] = {&pres, &res2, &pattern, &words, &seg_state, &sq_cnt, &sq_buf,
-                          &bk_cnt, &bk_start, &bk_buf, &carry, &bp_cur, &bp_table, &bp_index};
+                          &bk_cnt, &bk_start, &bk_buf, &bk_stage, &carry, &bp_cur, &bp_table,
+                          &bp_index};
         for (DevBuf *b : bufs)
             b->release();
         h_primes.clear();
@@ -312,8 +313,10 @@ struct SieveState {
             RCCHK(ensure(bk_cnt, (size_t)BK_WGS * (B / SEG) * 4));
             RCCHK(ensure(bk_start, (B / SEG + 1) * 4));
             RCCHK(ensure(bk_buf, (size_t)cap * 4 + 64));
+            RCCHK(ensure(bk_stage, (size_t)cap * 4 + 64));
         }
-        RCCHK(ensure(carry, 64));  // M(y1 - 1) at byte 0, segment ticket at byte 8
+        // M(y1 - 1) at byte 0, segment ticket at byte 8, bucket entry count at 16
+        RCCHK(ensure(carry, 64));
         RCCHK(ensure(bp_cur, ((size_t)nslots + MAX_WINDOWS) * sizeof(BlockParams)));
         RCCHK(ensure(bp_index, 64));
         return 0;
@@ -343,6 +346,7 @@ struct SieveState {
         b.bk_cnt = bk_cnt.as<uint32_t>();
         b.bk_start = bk_start.as<uint32_t>();
         b.bk_buf = bk_buf.as<uint32_t>();
+        b.bk_stage = bk_stage.as<uint32_t>();
         b.n_sq = count_primes_upto(isqrt_host(y2));
         b.n_sq_lds = std::min(count_primes_upto(SQ_LDS_P), b.n_sq);
         b.n_sq_lane = std::min(std::max(count_primes_upto(isqrt_host((uint64_t)b.nseg * SEG / 64)),
@@ -357,6 +361,7 @@ struct SieveState {
         b.sq_cnt = sq_cnt.as<uint32_t>();
         b.sq_buf = sq_buf.as<uint32_t>();
         b.seg_ticket = reinterpret_cast<uint32_t *>(carry.as<uint8_t>() + 8);
+        b.bk_total = reinterpret_cast<uint64_t *>(carry.as<uint8_t>() + 16);
         b.carry = carry.as<int64_t>();
         return b;
     }
@@ -400,7 +405,6 @@ struct SieveState {
         // length <= B can have, the lane kernel every prime of the table
         b.n_sq_lane = count_primes_upto(isqrt_host(B / 64));
         b.n_sq = (uint32_t)h_primes.size() + b.n_sq_lane;
-        b.n_sq = (uint32_t)h_primes.size();
         b.n_sieve = (uint32_t)h_primes.size();
         // capture the bucket kernels whenever some block may use them
         const uint32_t n_mid = count_primes_upto(SEG);
@@ -413,13 +417,15 @@ struct SieveState {
     // its fused M(y) prefix (an event may be recorded before it so the sieve
     // is timed alone).  set_params = false when a graph node loads the
     // parameters.
-    int sieve(const BlockArgs &b, hipStream_t s, hipEvent_t between, bool set_params = true) const
+    int sieve(const BlockArgs &b, hipStream_t s, hipEvent_t between, bool set_params = true,
+              hipEvent_t fill0 = nullptr, hipEvent_t fill1 = nullptr,
+              hipEvent_t fill2 = nullptr) const
     {
         if (set_params)
             HIPCHK(launch_block_set(params_of(b), const_cast<BlockParams *>(b.bp), s));
         HIPCHK(launch_block_setup(b, s));
         HIPCHK(launch_square_buckets(b, s));
-        HIPCHK(launch_prime_buckets(b, s));
+        HIPCHK(launch_prime_buckets(b, s, fill0, fill1, fill2));
         if (between)
             HIPCHK(hipEventRecord(between, s));
         HIPCHK(launch_sieve(b, s));
@@ -776,7 +782,7 @@ struct Ctx {
     std::vector<uint64_t> last_L, last_g0;
     std::vector<int64_t> last_j;  // index in the batch, -1 for n = 0
     bool last_valid = false;
-    double stats[16] = {0};
+    double stats[20] = {0};
     std::vector<hipEvent_t> events;
     Server srv;
 };
@@ -1013,6 +1019,8 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
     g.stats[13] = (double)nblocks;
     g.stats[14] = (double)pst[2];
     g.stats[15] = (double)pst[3];
+    for (int i = 16; i < 20; ++i)
+        g.stats[i] = 0;
     return 0;
 }
 
@@ -1300,6 +1308,7 @@ int mertens_init(uint64_t u, uint64_t block)
     g.u_req = u;
     g.block_req = block;
     g.tune = Tuning();
+    g.ss.bucket_min = SieveState().bucket_min;
     int rc = g.ss.ensure_pattern();
     if (rc == 0)
         rc = g.ss.ensure_primes(1024);
@@ -1418,7 +1427,7 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
     if (values)
         RCCHK(ensure(g.iv_vals, len * 8));
     const uint64_t nblocks = (b - start) / B + 1;
-    if (!event_at(3 * nblocks + 2)) {
+    if (!event_at(7 * nblocks + 2)) {
         set_error_text("hipEventCreate failed");
         return MERTENS_EIO;
     }
@@ -1427,13 +1436,20 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
     HIPCHK(hipEventRecord(g.events[ev++], s));
     RCCHK(g.ss.reset_carry(s));
     HIPCHK(launch_zero_u64(g.iv_part.as<uint64_t>(), (size_t)IV_WGS * 4, s));
-    std::vector<size_t> marks;
+    uint64_t *bk_total = reinterpret_cast<uint64_t *>(g.ss.carry.as<uint8_t>() + 16);
+    HIPCHK(launch_zero_u64(bk_total, 1, s));
+    std::vector<size_t> marks, fills;
+    double bucket_primes = 0;
     for (uint64_t y1 = start;; y1 += B) {
         const uint64_t y2 = b - y1 < B ? b : y1 + B - 1;
         const BlockArgs blk = g.ss.make_block(y1, y2);
+        bucket_primes += (double)(blk.n_sieve - blk.n_bucket);
+        if (blk.n_bucket < blk.n_sieve)
+            fills.push_back(ev + 4);
         marks.push_back(ev);
         HIPCHK(hipEventRecord(g.events[ev], s));
-        RCCHK(g.ss.sieve(blk, s, nullptr));
+        RCCHK(g.ss.sieve(blk, s, g.events[ev + 3], true, g.events[ev + 4], g.events[ev + 5],
+                         g.events[ev + 6]));
         HIPCHK(hipEventRecord(g.events[ev + 1], s));
         if (y1 == start)
             HIPCHK(launch_interval_base(blk, a, ma, off, s));
@@ -1445,13 +1461,15 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
         if (y2 == b)
             HIPCHK(launch_interval_final(blk, g.iv_part.as<uint64_t>(), b, off, res, s));
         HIPCHK(hipEventRecord(g.events[ev + 2], s));
-        ev += 3;
+        ev += 7;
         if (y2 == b)
             break;
     }
     HIPCHK(hipEventRecord(g.events[ev], s));
     int64_t h[5];
+    uint64_t entries = 0;
     HIPCHK(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&entries, bk_total, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (values)
         HIPCHK(hipMemcpy(values, g.iv_vals.p, len * 8, hipMemcpyDeviceToHost));
@@ -1465,19 +1483,29 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
         m_ext[0] = h[1];
         m_ext[1] = h[3];
     }
-    double t_sieve = 0, t_red = 0;
+    double t_sieve = 0, t_prep = 0, t_red = 0, t_fill = 0, t_regroup = 0;
     for (size_t m : marks) {
-        t_sieve += elapsed(m, m + 1);
+        t_prep += elapsed(m, m + 3);
+        t_sieve += elapsed(m + 3, m + 1);
         t_red += elapsed(m + 1, m + 2);
+    }
+    for (size_t f : fills) {
+        t_fill += elapsed(f, f + 1);
+        t_regroup += elapsed(f + 1, f + 2);
     }
     for (double &v : g.stats)
         v = 0;
     g.stats[0] = (double)(b - start + 1);
     g.stats[1] = (double)nblocks;
     g.stats[6] = t_sieve;
+    g.stats[8] = t_prep;
     g.stats[9] = t_red;
     g.stats[11] = elapsed(0, ev);
     g.stats[13] = (double)nblocks;
+    g.stats[16] = (double)entries;
+    g.stats[17] = t_fill;
+    g.stats[18] = bucket_primes;
+    g.stats[19] = t_regroup;
     return 0;
 }
 
@@ -1623,7 +1651,7 @@ int mertens_stats(double *vals, int cap)
 {
     if (!vals || cap <= 0)
         return 0;
-    const int k = std::min(cap, 16);
+    const int k = std::min(cap, 20);
     for (int i = 0; i < k; ++i)
         vals[i] = g.stats[i];
     return k;
