@@ -75,6 +75,25 @@ int mertens_init(uint64_t u, uint64_t block);
 int mertens_query(const uint64_t *n, size_t count, int64_t *out);
 
 /*
+ * mertens_query_wide -- mertens_query for arguments up to 2^96:
+ * n[i] = n_hi[i] 2^64 + n_lo[i] with n_hi[i] < 2^32 (Section 5 computes
+ * M(n) for n up to 10^22, past the 64-bit limit, with 128-bit integers).
+ *   n_lo, n_hi  host arrays of count words; out as in mertens_query.
+ * The x whose m = floor(n/x) needs more than 64 bits (x <= n / 2^64) get
+ * 128-bit entries of their own: K = max(k0 - 1, floor(beta sqrt(m)),
+ * floor(m / 2^32)) keeps Y = floor(m/(K+1)) below 2^32, so each run-length
+ * quotient is three 32-bit digit steps and each explicit-k quotient is an
+ * fp64 estimate with one exact 128-bit correction; every other x takes the
+ * plain path.  Arguments with n_hi = 0 behave exactly as in mertens_query,
+ * except that a batch holding any wide argument forms no keyed groups.
+ * The sieve bound n/(L+1) must stay below 2^50 (automatic u keeps it far
+ * lower).  Byproducts are available as after mertens_query.
+ * Returns 0, MERTENS_EINVAL (null pointer, n_hi >= 2^32, u out of range),
+ * MERTENS_ENOMEM, MERTENS_ENODEV, MERTENS_EIO.
+ */
+int mertens_query_wide(const uint64_t *n_lo, const uint64_t *n_hi, size_t count, int64_t *out);
+
+/*
  * mertens_byproducts -- the other entries of query i's array from the last
  * successful mertens_query (Section 1: one evaluation at n yields every
  * M(floor(n/c)); the array holds them for c <= L = max(1, floor(n/u))).
@@ -155,6 +174,10 @@ int mertens_set_stream(void *hip_stream);
  *                 (default 2^20; scanning them per segment is faster below)
  *   "rl_fast"     1 (default): run-length quotients with m < 2^48 take the
  *                 test-free rounded-up fp64 floor; 0: always the tested path
+ *   "wide_bits"   x with floor(n/x) >= 2^wide_bits take the 128-bit wide
+ *                 entries of mertens_query_wide (33..64; default 64, i.e.
+ *                 only those past 64 bits; lower values route more x there,
+ *                 for testing, and disable keyed groups)
  *   "serve_capacity"  most requests in flight for mertens_submit (4096)
  *   "serve_x_budget"  most x entries of admitted requests (2^26 = 4 GiB)
  *   "serve_short_blocks" requests whose sweep ends within this many blocks

@@ -129,6 +129,15 @@ struct QueryArgs {
     uint64_t *tile_items;               // items per tile, then exclusive prefix (ntiles+1)
     uint32_t *counter;                  // persistent work counter
     uint64_t *pair_stats;               // [0] y-side visits, [1] k pairs
+    // Wide arguments (n >= 2^64): per query the high word of n and the number
+    // xb of leading x whose m = floor(n/x) >= 2^wide_bits.  Those x take
+    // the wide entries below (m in 128 bits); their plain slots do no work.
+    const uint64_t *q_nhi, *q_xb;
+    uint32_t w_n;                                    // wide entries
+    const uint64_t *w_g;                             // per entry: global x index
+    const uint32_t *w_x, *w_q;                       // x and query
+    uint64_t *w_mlo, *w_mhi, *w_K, *w_Y, *w_k0;      // m (128 bits), K, Y, k0
+    uint64_t *w_klo, *w_khi;                         // k range of the current block
     // tuning
     double beta;
     uint32_t ychunk, kchunk;
@@ -154,6 +163,11 @@ hipError_t launch_prime_buckets(const BlockArgs &b, hipStream_t s, hipEvent_t fi
                                 hipEvent_t fill1 = nullptr, hipEvent_t fill2 = nullptr);
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s);
 hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
+// wide entries: plan (once per sweep), per-block k ranges and -K*M(Y), and
+// the per-block run-length and explicit-k sums
+hipError_t launch_wide_plan(const QueryArgs &q, hipStream_t s);
+hipError_t launch_wide_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
+hipError_t launch_wide_update(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
 hipError_t launch_scan_items(const QueryArgs &q, hipStream_t s);
 hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, hipStream_t s);
 // qlist = NULL finalizes queries 0..count-1, else the listed query indices

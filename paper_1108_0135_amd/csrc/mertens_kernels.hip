@@ -283,7 +283,21 @@ __global__ __launch_bounds__(UPD_THREADS) void k_plan(QueryArgs q)
         const uint64_t L = q.q_L[qi];
         // keyed entries carry x and m; plain tiles are x0, x0+1, ... of query qi
         const uint64_t x = x0 ? (uint64_t)x0 + lane : (uint64_t)q.key_x[g];
-        const uint64_t m = x0 ? q.q_n[qi] / x : q.x_m[g];
+        uint64_t m;
+        if (!x0) {
+            m = q.x_m[g];
+        } else if (x <= q.q_xb[qi]) {
+            m = 0;  // a wide entry carries this x; m = 0 gives K = k0 - 1, Y = 0: no work
+        } else if (q.q_nhi[qi]) {
+            // floor(n / x) < 2^64 for n = nhi 2^64 + n_lo (nhi < x < 2^32), in two
+            // 32-bit digit steps
+            const uint64_t nlo = q.q_n[qi];
+            const uint64_t a1 = (q.q_nhi[qi] << 32) | (nlo >> 32);
+            const uint64_t a0 = ((a1 % x) << 32) | (nlo & 0xFFFFFFFFull);
+            m = ((a1 / x) << 32) | (a0 / x);
+        } else {
+            m = q.q_n[qi] / x;
+        }
         const uint64_t k0 = L / x + 1;
         uint64_t K = (uint64_t)(q.beta * (double)isqrt64(m));
         if (K < k0 - 1)
@@ -988,6 +1002,199 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockA
         q.tile_nmu[tile] = (uint32_t)nmu;
         q.tile_items[tile] = nmu + nk;
     }
+}
+
+// ====================================================================
+// Wide entries: x whose m = floor(n/x) needs more than 64 bits (n up to
+// 2^96), or at least 2^wide_bits.  Same split as the plain path (Section
+// 2): K = max(k0 - 1, floor(beta sqrt(m)), floor(m / 2^32)), so Y =
+// floor(m/(K+1)) < 2^32 and every run-length quotient is three 32-bit
+// digit steps; explicit-k quotients are below the sieve bound (< 2^64).
+// ====================================================================
+struct U128 {
+    uint64_t lo, hi;
+};
+
+__device__ inline bool u128_less(U128 a, U128 b)
+{
+    return a.hi != b.hi ? a.hi < b.hi : a.lo < b.lo;
+}
+
+__device__ inline U128 mul64(uint64_t a, uint64_t b)
+{
+    return U128{a * b, __umul64hi(a, b)};
+}
+
+// floor(a / d) for any a and d >= 1, one quotient bit per step (used once per
+// entry and block only).
+__device__ inline U128 udiv128_bits(U128 a, uint64_t d)
+{
+    U128 q{0, 0};
+    uint64_t r = 0;
+    for (int i = 127; i >= 0; --i) {
+        const uint64_t bit = i >= 64 ? (a.hi >> (i - 64)) & 1u : (a.lo >> i) & 1u;
+        const bool carry = r >> 63;  // r * 2 + bit would not fit 64 bits
+        r = (r << 1) | bit;
+        if (carry || r >= d) {
+            r -= d;  // the true value minus d is below d, so wrapping is exact
+            if (i >= 64)
+                q.hi |= 1ull << (i - 64);
+            else
+                q.lo |= 1ull << i;
+        }
+    }
+    return q;
+}
+
+// One digit step: floor(a / y) and a mod y for a < y 2^32, y < 2^32, from an
+// fp64 estimate (error below one) and one integer correction.
+__device__ inline uint64_t digit_div(uint64_t a, uint64_t y, double rcp, uint64_t &r)
+{
+    uint64_t q = (uint64_t)((double)a * rcp);
+    r = a - q * y;
+    if ((int64_t)r < 0) {
+        --q;
+        r += y;
+    } else if (r >= y) {
+        ++q;
+        r -= y;
+    }
+    return q;
+}
+
+// floor(m / y) mod 2^64 for m < 2^96 and 1 <= y < 2^32.
+__device__ inline uint64_t wide_quot_low(U128 m, uint64_t y)
+{
+    const double rcp = 1.0 / (double)y;
+    uint64_t r;
+    (void)digit_div(m.hi, y, rcp, r);
+    const uint64_t q1 = digit_div((r << 32) | (m.lo >> 32), y, rcp, r);
+    const uint64_t q0 = digit_div((r << 32) | (m.lo & 0xFFFFFFFFull), y, rcp, r);
+    return (q1 << 32) + q0;
+}
+
+// floor(m / k) for a quotient below 2^50: fp64 estimate, then the exact
+// 128-bit check either way.
+__device__ inline uint64_t wide_quot_small(U128 m, double md, uint64_t k)
+{
+    uint64_t q = (uint64_t)(md / (double)k);
+    if (u128_less(m, mul64(k, q)))
+        --q;
+    else if (!u128_less(m, mul64(k, q + 1)))
+        ++q;
+    return q;
+}
+
+__global__ void k_wide_plan(QueryArgs q)
+{
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= q.w_n)
+        return;
+    const uint32_t qi = q.w_q[e];
+    const uint64_t x = q.w_x[e];
+    const U128 m = udiv128_bits(U128{q.q_n[qi], q.q_nhi[qi]}, x);
+    const uint64_t k0 = q.q_L[qi] / x + 1;
+    uint64_t K = (m.hi << 32) | (m.lo >> 32);
+    const double md = (double)m.hi * 18446744073709551616.0 + (double)m.lo;
+    const double kb = q.beta * sqrt(md);
+    if (kb < 1.8e19 && (uint64_t)kb > K)
+        K = (uint64_t)kb;
+    if (K < k0 - 1)
+        K = k0 - 1;
+    const U128 Y = udiv128_bits(m, K + 1);
+    q.w_mlo[e] = m.lo;
+    q.w_mhi[e] = m.hi;
+    q.w_K[e] = K;
+    q.w_k0[e] = k0;
+    q.w_Y[e] = Y.lo;  // < 2^32
+}
+
+hipError_t launch_wide_plan(const QueryArgs &q, hipStream_t s)
+{
+    if (q.w_n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_wide_plan, dim3((q.w_n + 63) / 64), dim3(64), 0, s, q);
+    return hipGetLastError();
+}
+
+// Per entry: the k with floor(m/k) in [y1, y2] (k in [floor(m/(y2+1)) + 1,
+// floor(m/y1)], within [k0, K]), and -K M(Y) when Y is in the block.
+__global__ void k_wide_prep(QueryArgs q, BlockArgs b_in)
+{
+    const BlockArgs b = load_block(b_in);
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= q.w_n)
+        return;
+    const U128 m{q.w_mlo[e], q.w_mhi[e]};
+    const uint64_t K = q.w_K[e], k0 = q.w_k0[e], Y = q.w_Y[e];
+    const uint64_t y1e = b.y1 > 0 ? b.y1 : 1;
+    const U128 lo = udiv128_bits(m, b.y2 + 1), hi = udiv128_bits(m, y1e);
+    uint64_t klo = (lo.hi || lo.lo == ~0ull) ? ~0ull : lo.lo + 1;
+    if (klo < k0)
+        klo = k0;
+    const uint64_t khi = (hi.hi || hi.lo > K) ? K : hi.lo;
+    q.w_klo[e] = klo;
+    q.w_khi[e] = khi;
+    if (Y >= y1e && Y <= b.y2)
+        q.S[q.w_g[e]] -= K * (uint64_t)M_at(b.words, Y - b.y1);
+}
+
+hipError_t launch_wide_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s)
+{
+    if (q.w_n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_wide_prep, dim3((q.w_n + 63) / 64), dim3(64), 0, s, q, b);
+    return hipGetLastError();
+}
+
+// Per entry, over the whole grid: the explicit-k terms M(floor(m/k)) and the
+// run-length terms floor(m/y) mu(y) for y in the block up to Y; one atomic
+// per wave and entry into S.
+constexpr uint32_t WIDE_WGS = 1024;
+
+__global__ __launch_bounds__(256) void k_wide_update(QueryArgs q, BlockArgs b_in)
+{
+    const BlockArgs b = load_block(b_in);
+    const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint64_t y1e = b.y1 > 0 ? b.y1 : 1;
+    for (uint32_t e = 0; e < q.w_n; ++e) {
+        const uint64_t klo = q.w_klo[e], khi = q.w_khi[e];
+        const uint64_t yhi = q.w_Y[e] < b.y2 ? q.w_Y[e] : b.y2;
+        if (klo > khi && y1e > yhi)
+            continue;
+        const U128 m{q.w_mlo[e], q.w_mhi[e]};
+        uint64_t acc = 0;
+        if (klo <= khi) {
+            const double md = (double)m.hi * 18446744073709551616.0 + (double)m.lo;
+            for (uint64_t k = klo + gid; k <= khi; k += stride) {
+                const uint64_t t = wide_quot_small(m, md, k);
+                if (t >= b.y1 && t <= b.y2)  // always, by the choice of [klo, khi]
+                    acc += (uint64_t)M_at(b.words, t - b.y1);
+            }
+        }
+        for (uint64_t y = y1e + gid; y <= yhi; y += stride) {
+            const uint64_t off = y - b.y1;
+            const uint64_t rec = b.words[2 * (off >> 5)];
+            const uint32_t bt = (uint32_t)(off & 31);
+            const bool pos = (rec >> bt) & 1u, neg = (rec >> (32 + bt)) & 1u;
+            if (pos || neg) {
+                const uint64_t t = wide_quot_low(m, y);
+                acc += pos ? t : 0 - t;
+            }
+        }
+        acc = wave_sum_u64(acc);
+        if (lane_id() == 0 && acc)
+            atomicAdd(reinterpret_cast<unsigned long long *>(&q.S[q.w_g[e]]), acc);
+    }
+}
+
+hipError_t launch_wide_update(const QueryArgs &q, const BlockArgs &b, hipStream_t s)
+{
+    if (q.w_n == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_wide_update, dim3(WIDE_WGS), dim3(256), 0, s, q, b);
+    return hipGetLastError();
 }
 
 hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s)

@@ -171,6 +171,9 @@ struct Tuning {
     uint32_t update_window = 0;
     uint64_t window_ymax = 1ull << 30;
     uint32_t rl_fast = 1;
+    // x with floor(n/x) >= 2^wide_bits go through the 128-bit wide entries
+    // (64: exactly those that need more than 64 bits)
+    uint32_t wide_bits = 64;
     bool graph = false;  // replay one captured hipGraph per block
 };
 
@@ -443,13 +446,15 @@ struct SieveState {
 // One set of queries sharing a sweep: per-query plan and device state.
 // ---------------------------------------------------------------------------
 struct Batch {
-    std::vector<uint64_t> n, L, g0, ymax, koff;
+    std::vector<uint64_t> n, nhi, xb, L, g0, ymax, koff;
+    uint32_t nwide = 0;
     std::vector<uint32_t> fin_list;  // plain queries and one member per keyed group
     uint64_t X = 0, ymax_all = 0, keyed_entries = 0;
     uint32_t ntiles = 0;
     DevBuf q_n, q_L, q_g0, q_koff, x_m, x_Y, x_K, x_k0, S, A, x_klo, x_khi, key_x, key_off;
     DevBuf tile_q, tile_x0, tile_nx, tile_g0, tile_ymax, tile_klo, tile_khi, tile_mode, tile_nmu,
         tile_items, counter, pair_stats, out_dev, qlist, byp;
+    DevBuf q_nhi, q_xb, w_g, w_x, w_q, w_mlo, w_mhi, w_K, w_Y, w_k0, w_klo, w_khi;
     QueryArgs args{};
 
     void release()
@@ -457,7 +462,8 @@ struct Batch {
         DevBuf *bufs[] = {&q_n, &q_L, &q_g0, &q_koff, &x_m, &x_Y, &x_K, &x_k0, &S, &A, &x_klo,
                           &x_khi, &key_x, &key_off, &tile_q, &tile_x0, &tile_nx, &tile_g0,
                           &tile_ymax, &tile_klo, &tile_khi, &tile_mode, &tile_nmu, &tile_items,
-                          &counter, &pair_stats, &out_dev, &qlist, &byp};
+                          &counter, &pair_stats, &out_dev, &qlist, &byp, &q_nhi, &q_xb,
+                          &w_g, &w_x, &w_q, &w_mlo, &w_mhi, &w_K, &w_Y, &w_k0, &w_klo, &w_khi};
         for (DevBuf *b : bufs)
             b->release();
     }
@@ -500,10 +506,18 @@ struct Batch {
     // on x and floor(n/x) only), so a dense window of n costs its distinct
     // quotients rather than one array per n.
     int plan(const std::vector<uint64_t> &ns, const std::vector<uint64_t> &us, const Tuning &t,
-             hipStream_t s, bool group = true)
+             hipStream_t s, bool group = true, const std::vector<uint64_t> *ns_hi = nullptr)
     {
         const size_t nq = ns.size();
         n = ns;
+        nhi.assign(nq, 0);
+        if (ns_hi)
+            nhi = *ns_hi;
+        xb.assign(nq, 0);
+        bool wide = t.wide_bits < 64;
+        for (uint64_t h : nhi)
+            wide = wide || h != 0;
+        group = group && !wide;  // keyed groups take 64-bit arguments only
         L.assign(nq, 0);
         g0.assign(nq, 0);
         ymax.assign(nq, 0);
@@ -513,16 +527,23 @@ struct Batch {
         ymax_all = 0;
         keyed_entries = 0;
         for (size_t i = 0; i < nq; ++i) {
-            uint64_t Li = ns[i] / us[i];
-            if (Li < 1)
-                Li = 1;
-            if (Li >= (1ull << 31)) {
+            const unsigned __int128 N = ((unsigned __int128)nhi[i] << 64) | ns[i];
+            const unsigned __int128 Lw = N / us[i];
+            if (Lw >= (1ull << 31)) {
                 set_error_text("u too small: some n would need an array of 2^31 or more entries");
                 return MERTENS_EINVAL;
             }
+            const uint64_t Li = Lw < 1 ? 1 : (uint64_t)Lw;
             L[i] = Li;
-            ymax[i] = ns[i] / (Li + 1);
+            const unsigned __int128 ym = N / (Li + 1);
+            if (ym >> 62) {
+                set_error_text("u too large: the sieve bound n/(L+1) must stay below 2^62");
+                return MERTENS_EINVAL;
+            }
+            ymax[i] = (uint64_t)ym;
             ymax_all = std::max(ymax_all, ymax[i]);
+            const unsigned __int128 nb = N >> t.wide_bits;  // x <= nb have m >= 2^wide_bits
+            xb[i] = nb < Li ? (uint64_t)nb : Li;
         }
         // groups of equal L (ascending n inside a group)
         std::vector<size_t> order(nq);
@@ -585,6 +606,24 @@ struct Batch {
             }
             a = b;
         }
+        // wide entries: x = 1..xb of every query
+        std::vector<uint64_t> h_wg;
+        std::vector<uint32_t> h_wx, h_wq;
+        for (size_t i = 0; i < nq; ++i)
+            for (uint64_t x = 1; x <= xb[i]; ++x) {
+                if (h_wg.size() >= (1u << 24)) {
+                    set_error_text("too many wide entries (x with floor(n/x) >= 2^wide_bits)");
+                    return MERTENS_EINVAL;
+                }
+                h_wg.push_back(g0[i] + x - 1);
+                h_wx.push_back((uint32_t)x);
+                h_wq.push_back((uint32_t)i);
+            }
+        nwide = (uint32_t)h_wg.size();
+        if (nwide && ymax_all >= (1ull << 50)) {
+            set_error_text("wide arguments need a sieve bound n/(L+1) below 2^50");
+            return MERTENS_EINVAL;
+        }
         const size_t nt = t_q.size();
         if (nt >= (1ull << 31)) {
             set_error_text("too many tiles");
@@ -595,8 +634,8 @@ struct Batch {
         RCCHK(ensure(q_L, nq * 8));
         RCCHK(ensure(q_g0, nq * 8));
         RCCHK(ensure(q_koff, nq * 8));
-        DevBuf *xb[] = {&x_m, &x_Y, &x_K, &x_k0, &S, &A, &x_klo, &x_khi};
-        for (DevBuf *b : xb)
+        DevBuf *xbufs[] = {&x_m, &x_Y, &x_K, &x_k0, &S, &A, &x_klo, &x_khi};
+        for (DevBuf *b : xbufs)
             RCCHK(ensure(*b, X * 8));
         RCCHK(ensure(key_x, std::max<uint64_t>(X, 1) * 4));
         RCCHK(ensure(key_off, std::max<size_t>(h_key_off.size(), 1) * 4));
@@ -614,6 +653,21 @@ struct Batch {
         RCCHK(ensure(pair_stats, 64));
         RCCHK(ensure(out_dev, nq * 8));
         RCCHK(ensure(qlist, nq * 4));
+        RCCHK(ensure(q_nhi, nq * 8));
+        RCCHK(ensure(q_xb, nq * 8));
+        const size_t nw1 = std::max<size_t>(nwide, 1);
+        DevBuf *wb[] = {&w_g, &w_mlo, &w_mhi, &w_K, &w_Y, &w_k0, &w_klo, &w_khi};
+        for (DevBuf *b : wb)
+            RCCHK(ensure(*b, nw1 * 8));
+        RCCHK(ensure(w_x, nw1 * 4));
+        RCCHK(ensure(w_q, nw1 * 4));
+        HIPCHK(hipMemcpyAsync(q_nhi.p, nhi.data(), nq * 8, hipMemcpyHostToDevice, s));
+        HIPCHK(hipMemcpyAsync(q_xb.p, xb.data(), nq * 8, hipMemcpyHostToDevice, s));
+        if (nwide) {
+            HIPCHK(hipMemcpyAsync(w_g.p, h_wg.data(), nwide * 8, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(w_x.p, h_wx.data(), nwide * 4, hipMemcpyHostToDevice, s));
+            HIPCHK(hipMemcpyAsync(w_q.p, h_wq.data(), nwide * 4, hipMemcpyHostToDevice, s));
+        }
         HIPCHK(hipMemcpyAsync(q_n.p, n.data(), nq * 8, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(q_L.p, L.data(), nq * 8, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(q_g0.p, g0.data(), nq * 8, hipMemcpyHostToDevice, s));
@@ -663,6 +717,19 @@ struct Batch {
         q.tile_items = tile_items.as<uint64_t>();
         q.counter = counter.as<uint32_t>();
         q.pair_stats = pair_stats.as<uint64_t>();
+        q.q_nhi = q_nhi.as<uint64_t>();
+        q.q_xb = q_xb.as<uint64_t>();
+        q.w_n = nwide;
+        q.w_g = w_g.as<uint64_t>();
+        q.w_x = w_x.as<uint32_t>();
+        q.w_q = w_q.as<uint32_t>();
+        q.w_mlo = w_mlo.as<uint64_t>();
+        q.w_mhi = w_mhi.as<uint64_t>();
+        q.w_K = w_K.as<uint64_t>();
+        q.w_Y = w_Y.as<uint64_t>();
+        q.w_k0 = w_k0.as<uint64_t>();
+        q.w_klo = w_klo.as<uint64_t>();
+        q.w_khi = w_khi.as<uint64_t>();
         q.beta = t.beta;
         q.ychunk = t.ychunk;
         q.kchunk = t.kchunk;
@@ -670,6 +737,7 @@ struct Batch {
         q.kbal = t.kbal;
         HIPCHK(launch_zero_u64(pair_stats.as<uint64_t>(), 4, s));
         HIPCHK(launch_plan(q, s));
+        HIPCHK(launch_wide_plan(q, s));
         return 0;
     }
 
@@ -681,6 +749,8 @@ struct Batch {
         if (mid)
             HIPCHK(hipEventRecord(mid, s));
         HIPCHK(launch_update(args, b, grid, s));
+        HIPCHK(launch_wide_prep(args, b, s));
+        HIPCHK(launch_wide_update(args, b, s));
         return 0;
     }
 
@@ -876,15 +946,23 @@ bool slot_events(uint32_t slots)
 
 // The synchronous sweep for nonzero arguments ns[]: fills A on the device
 // and the results into res[] (host).
-int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res)
+int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
+              const std::vector<uint64_t> *ns_hi = nullptr)
 {
     const size_t nq = ns.size();
     uint64_t u = g.u_req;
-    if (u == 0)
-        u = auto_u(effective_total_n(ns), g.tune.u_scale);
+    if (u == 0) {
+        long double total = 0;
+        if (ns_hi)
+            for (size_t i = 0; i < nq; ++i)
+                total += (long double)(*ns_hi)[i] * 18446744073709551616.0L + (long double)ns[i];
+        else
+            total = effective_total_n(ns);
+        u = auto_u(total, g.tune.u_scale);
+    }
     hipStream_t s = g.stream;
     Batch &bt = g.batch;
-    RCCHK(bt.plan(ns, std::vector<uint64_t>(nq, u), g.tune, s));
+    RCCHK(bt.plan(ns, std::vector<uint64_t>(nq, u), g.tune, s, true, ns_hi));
     const uint64_t ymax = bt.ymax_all;
     RCCHK(g.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(ymax), 1024)));
     RCCHK(g.ss.ensure_pattern());
@@ -1361,6 +1439,53 @@ int mertens_query(const uint64_t *n, size_t count, int64_t *out)
     return 0;
 }
 
+int mertens_query_wide(const uint64_t *n_lo, const uint64_t *n_hi, size_t count, int64_t *out)
+{
+    if (count == 0)
+        return 0;
+    if (!n_lo || !n_hi || !out) {
+        set_error_text("null pointer with count > 0");
+        return MERTENS_EINVAL;
+    }
+    for (size_t i = 0; i < count; ++i)
+        if (n_hi[i] >> 32) {
+            set_error_text("wide arguments must be below 2^96");
+            return MERTENS_EINVAL;
+        }
+    if (!g.ready) {
+        set_error_text("mertens_init has not been called");
+        return MERTENS_ENODEV;
+    }
+    std::vector<uint64_t> lo, hi;
+    std::vector<size_t> where;
+    for (size_t i = 0; i < count; ++i)
+        if (n_lo[i] != 0 || n_hi[i] != 0) {
+            lo.push_back(n_lo[i]);
+            hi.push_back(n_hi[i]);
+            where.push_back(i);
+        }
+    std::vector<int64_t> res;
+    g.last_valid = false;
+    if (!lo.empty()) {
+        int rc = run_query(lo, res, &hi);
+        if (rc != 0)
+            return rc;
+    }
+    g.last_L.assign(count, 0);
+    g.last_g0.assign(count, 0);
+    g.last_j.assign(count, -1);
+    for (size_t i = 0; i < count; ++i)
+        out[i] = 0;
+    for (size_t j = 0; j < where.size(); ++j) {
+        out[where[j]] = res[j];
+        g.last_L[where[j]] = g.batch.L[j];
+        g.last_g0[where[j]] = g.batch.g0[j];
+        g.last_j[where[j]] = (int64_t)j;
+    }
+    g.last_valid = true;
+    return 0;
+}
+
 int mertens_byproducts(size_t i, int64_t *buf, size_t cap, size_t *len)
 {
     if (!g.ready)
@@ -1589,6 +1714,10 @@ int mertens_set_param(const char *key, double value)
         if (!(value == 0.0 || value == 1.0))
             return MERTENS_EINVAL;
         g.tune.graph = value != 0.0;
+    } else if (!strcmp(key, "wide_bits")) {
+        if (!(value >= 33.0 && value <= 64.0 && value == std::floor(value)))
+            return MERTENS_EINVAL;
+        g.tune.wide_bits = (uint32_t)value;
     } else if (!strcmp(key, "beta")) {
         if (!(value > 0.0 && value <= 1.0))
             return MERTENS_EINVAL;

@@ -8,12 +8,15 @@ from __future__ import annotations
 
 import numpy as np
 
-# Powers of ten whose M(n) Table 1 of the paper prints (all below 2^64).
+# Powers of ten whose M(n) Table 1 of the paper prints (10^20..10^22 exceed 2^64).
 TABLE1 = {
     10**16: -3195437,
     10**17: -21830254,
     10**18: -46758740,
     10**19: 899990187,
+    10**20: 461113106,
+    10**21: 3395895277,
+    10**22: -2061910120,
 }
 # Section 6: the new extreme value, M(11609864264058592345) = -1,995,900,927.
 EXTREME_N = 11609864264058592345

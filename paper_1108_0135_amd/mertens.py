@@ -33,6 +33,7 @@ _sig = {
     "mertens_init": ([_u64, _u64], ctypes.c_int),
     "mertens_query": ([_P(_u64), _sz, _P(_i64)], ctypes.c_int),
     "mertens_byproducts": ([_sz, _P(_i64), _sz, _P(_sz)], ctypes.c_int),
+    "mertens_query_wide": ([_P(_u64), _P(_u64), _sz, _P(_i64)], ctypes.c_int),
     "mertens_set_stream": ([ctypes.c_void_p], ctypes.c_int),
     "mertens_set_param": ([ctypes.c_char_p, ctypes.c_double], ctypes.c_int),
     "mertens_stats": ([_P(ctypes.c_double), ctypes.c_int], ctypes.c_int),
@@ -92,6 +93,17 @@ def query(ns) -> np.ndarray:
     arr = np.ascontiguousarray(np.asarray(ns, dtype=np.uint64).reshape(-1))
     out = np.zeros(arr.size, dtype=np.int64)
     _check(_lib.mertens_query(_u64p(arr), arr.size, _i64p(out)), "mertens_query")
+    return out
+
+
+def query_wide(ns) -> np.ndarray:
+    """Exact M(n) for Python ints 0 <= n < 2^96 (words split here, one shared sweep)."""
+    ns = [int(v) for v in ns]
+    lo = np.array([v & (2**64 - 1) for v in ns], dtype=np.uint64)
+    hi = np.array([v >> 64 for v in ns], dtype=np.uint64)
+    out = np.zeros(len(ns), dtype=np.int64)
+    _check(_lib.mertens_query_wide(_u64p(lo), _u64p(hi), len(ns), _i64p(out)),
+           "mertens_query_wide")
     return out
 
 

@@ -51,6 +51,14 @@ def test_bad_arguments_without_gpu():
         use = cap > 0
         assert lib.mertens_interval(a, b, None, None, None, None,
                                     mt._i64p(vals) if use else None, cap) == mt.EINVAL, (a, b)
+    # wide arguments: n_hi < 2^32; wide_bits in 33..64
+    lo = np.array([1], dtype=np.uint64)
+    hi = np.array([1 << 32], dtype=np.uint64)
+    out = np.zeros(1, dtype=np.int64)
+    assert lib.mertens_query_wide(mt._u64p(lo), mt._u64p(hi), 1, mt._i64p(out)) == mt.EINVAL
+    assert lib.mertens_query_wide(None, None, 0, None) == 0
+    for bad in (32.0, 65.0, 40.5):
+        assert lib.mertens_set_param(b"wide_bits", bad) == mt.EINVAL, bad
     # divisor outside [1, 2^32)
     n = np.array([5], dtype=np.uint64)
     for bad in (0, 1 << 32):

@@ -334,3 +334,43 @@ def test_interval_section6_extreme_window(mt):
     assert int(got["values"][0]) == g["m_a"]
     for n, m in g["samples"].items():
         assert int(got["values"][int(n) - g["a"]]) == m, n
+
+
+# ------------------------------------------------------------------ arguments past 2^64
+
+def test_wide_entries_vs_golden(mt):
+    # every x with floor(n/x) >= 2^33 goes through the 128-bit wide entries
+    # (the path arguments past 2^64 take), at sizes the oracle reaches
+    g = GOLDEN["n1e12"]
+    _reinit(mt, u=10**8, wide_bits=33)
+    assert int(mt.query_wide([g["n"]])[0]) == g["M"]
+    assert list(mt.byproducts(0)) == g["byproducts"]
+    _reinit(mt, wide_bits=33)
+    b = GOLDEN["batch48"]
+    assert list(mt.query_wide(b["n"])) == b["M"]
+    s = GOLDEN["seeded32"]
+    _reinit(mt, u=10**5, block=1 << 17, wide_bits=33)
+    assert list(mt.query_wide(s["n"])) == s["M"]
+
+
+def test_wide_entries_graph_replay(mt):
+    g = GOLDEN["n1e12"]
+    for _ in range(2):
+        _reinit(mt, u=10**8, block=1 << 22, wide_bits=33, graph=1)
+        assert int(mt.query_wide([g["n"]])[0]) == g["M"]
+
+
+def test_query_wide_low_words_match_query(mt):
+    _reinit(mt)
+    ns = GOLDEN["seeded32"]["n"] + [10**12, 10**16]
+    assert list(mt.query_wide(ns)) == list(mt.query(ns))
+
+
+def test_table1_1e20_and_byproducts(mt):
+    # Table 1: M(10^20) = 461113106; its byproducts M(10^20 / c) give the
+    # printed M(10^19), M(10^18), M(10^17), M(10^16) (Section 1)
+    _reinit(mt)
+    assert int(mt.query_wide([10**20])[0]) == inputs.TABLE1[10**20]
+    byp = mt.byproducts(0)
+    assert [int(byp[c - 1]) for c in (10, 100, 1000, 10**4)] == [
+        inputs.TABLE1[10**19], inputs.TABLE1[10**18], inputs.TABLE1[10**17], inputs.TABLE1[10**16]]
