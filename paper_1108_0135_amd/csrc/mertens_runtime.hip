@@ -174,6 +174,9 @@ struct Tuning {
     // x with floor(n/x) >= 2^wide_bits go through the 128-bit wide entries
     // (64: exactly those that need more than 64 bits)
     uint32_t wide_bits = 64;
+    // > 0: wait for every progress-th block of a query and report it on
+    // stderr (for sweeps that run many minutes)
+    uint64_t progress = 0;
     bool graph = false;  // replay one captured hipGraph per block
 };
 
@@ -972,12 +975,16 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     RCCHK(g.ss.ensure_blocks(B, slots));
     const uint32_t grid = update_grid(g.ncu, g.tune);
 
-    size_t ev = 0;
-    if (!event_at(5 * nblocks + 3) || !slot_events(slots)) {
+    // timing events: [0] start, [1]/[2] around finalize, then five per block
+    // in a ring of EV_RING blocks (a block's times are added up before its
+    // slot is reused)
+    constexpr uint64_t EV_RING = 4096;
+    const uint64_t nring = std::min<uint64_t>(nblocks, EV_RING);
+    if (!event_at(3 + 5 * nring) || !slot_events(slots)) {
         set_error_text("hipEventCreate failed");
         return MERTENS_EIO;
     }
-    HIPCHK(hipEventRecord(g.events[ev++], s));
+    HIPCHK(hipEventRecord(g.events[0], s));
     // one record slot: everything in turn on one stream (no cross-stream
     // waits between the sieve and the update of a block)
     const bool ahead = !g.tune.graph && slots > 1;
@@ -985,8 +992,12 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     if (ahead)
         HIPCHK(hipStreamWaitEvent(ss, g.events[0], 0));  // after the plan
     RCCHK(g.ss.reset_carry(ss));
-    std::vector<size_t> marks;
-    marks.reserve(nblocks);
+    double t_sieve = 0, t_scan = 0, t_prep = 0, t_upd = 0;
+    auto add_times = [&](size_t m) {
+        t_sieve += elapsed(m, m + 1);
+        t_prep += elapsed(m + 2, m + 3);
+        t_upd += elapsed(m + 3, m + 4);
+    };
     if (g.tune.graph) {
         // one captured graph of the whole block pipeline, replayed per block;
         // its first node loads the block's parameters from a table
@@ -1034,7 +1045,11 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
         const uint64_t y2 = std::min(y1 + B - 1, ymax);
         const uint32_t slot = (uint32_t)(bi % slots);
         const BlockArgs b = g.ss.make_block(y1, y2, slot);
-        marks.push_back(ev);
+        const size_t ev = 3 + 5 * (size_t)(bi % EV_RING);
+        if (bi >= EV_RING) {  // the slot's previous block: wait for it, keep its times
+            HIPCHK(hipEventSynchronize(g.events[ev + 4]));
+            add_times(ev);
+        }
         if (ahead && bi >= slots)
             HIPCHK(hipStreamWaitEvent(ss, g.updated_ev[slot], 0));
         RCCHK(g.ss.sieve(b, ss, g.events[ev]));
@@ -1060,11 +1075,16 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
         HIPCHK(hipEventRecord(g.events[ev + 4], s));
         if (ahead)
             HIPCHK(hipEventRecord(g.updated_ev[slot], s));
-        ev += 5;
+        if (g.tune.progress && (bi + 1) % g.tune.progress == 0) {
+            HIPCHK(hipEventSynchronize(g.events[ev + 4]));
+            fprintf(stderr, "mertens: block %llu of %llu updated\n", (unsigned long long)(bi + 1),
+                    (unsigned long long)nblocks);
+            fflush(stderr);
+        }
     }
-    HIPCHK(hipEventRecord(g.events[ev], s));
+    HIPCHK(hipEventRecord(g.events[1], s));
     RCCHK(bt.finalize({}, s));
-    HIPCHK(hipEventRecord(g.events[ev + 1], s));
+    HIPCHK(hipEventRecord(g.events[2], s));
     res.resize(nq);
     uint64_t pst[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(res.data(), bt.out_dev.p, nq * 8, hipMemcpyDeviceToHost, s));
@@ -1075,12 +1095,9 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
 
     // kernel times per stream; with sieve-ahead they overlap, so their sum
     // can exceed the total
-    double t_sieve = 0, t_scan = 0, t_prep = 0, t_upd = 0;
-    for (size_t m : marks) {
-        t_sieve += elapsed(m, m + 1);
-        t_prep += elapsed(m + 2, m + 3);
-        t_upd += elapsed(m + 3, m + 4);
-    }
+    if (!g.tune.graph)
+        for (uint64_t bj = nblocks - nring; bj < nblocks; ++bj)
+            add_times(3 + 5 * (size_t)(bj % EV_RING));
     g.stats[0] = (double)(ymax + 1);
     g.stats[1] = (double)nblocks;
     g.stats[2] = (double)u;
@@ -1091,8 +1108,8 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     g.stats[7] = t_scan;
     g.stats[8] = t_prep;
     g.stats[9] = t_upd;
-    g.stats[10] = elapsed(ev, ev + 1);
-    g.stats[11] = elapsed(0, ev + 1);
+    g.stats[10] = elapsed(1, 2);
+    g.stats[11] = elapsed(0, 2);
     g.stats[12] = (double)nblocks;
     g.stats[13] = (double)nblocks;
     g.stats[14] = (double)pst[2];
@@ -1552,26 +1569,44 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
     if (values)
         RCCHK(ensure(g.iv_vals, len * 8));
     const uint64_t nblocks = (b - start) / B + 1;
-    if (!event_at(7 * nblocks + 2)) {
+    // timing events: [0] start, [1] end, then seven per block in a ring of
+    // EV_RING blocks (a block's times are added up before its slot is reused)
+    constexpr uint64_t EV_RING = 4096;
+    const uint64_t nring = std::min<uint64_t>(nblocks, EV_RING);
+    if (!event_at(2 + 7 * nring)) {
         set_error_text("hipEventCreate failed");
         return MERTENS_EIO;
     }
     int64_t *off = g.iv_small.as<int64_t>(), *res = off + 1;
-    size_t ev = 0;
-    HIPCHK(hipEventRecord(g.events[ev++], s));
+    HIPCHK(hipEventRecord(g.events[0], s));
     RCCHK(g.ss.reset_carry(s));
     HIPCHK(launch_zero_u64(g.iv_part.as<uint64_t>(), (size_t)IV_WGS * 4, s));
     uint64_t *bk_total = reinterpret_cast<uint64_t *>(g.ss.carry.as<uint8_t>() + 16);
     HIPCHK(launch_zero_u64(bk_total, 1, s));
-    std::vector<size_t> marks, fills;
+    double t_sieve = 0, t_prep = 0, t_red = 0, t_fill = 0, t_regroup = 0;
+    std::vector<uint8_t> filled(nring, 0);  // per ring slot: its block used buckets
+    auto add_times = [&](uint64_t bj) {
+        const size_t m = 2 + 7 * (size_t)(bj % EV_RING);
+        t_prep += elapsed(m, m + 3);
+        t_sieve += elapsed(m + 3, m + 1);
+        t_red += elapsed(m + 1, m + 2);
+        if (filled[bj % EV_RING]) {
+            t_fill += elapsed(m + 4, m + 5);
+            t_regroup += elapsed(m + 5, m + 6);
+        }
+    };
     double bucket_primes = 0;
-    for (uint64_t y1 = start;; y1 += B) {
+    uint64_t bi = 0;
+    for (uint64_t y1 = start;; y1 += B, ++bi) {
         const uint64_t y2 = b - y1 < B ? b : y1 + B - 1;
         const BlockArgs blk = g.ss.make_block(y1, y2);
         bucket_primes += (double)(blk.n_sieve - blk.n_bucket);
-        if (blk.n_bucket < blk.n_sieve)
-            fills.push_back(ev + 4);
-        marks.push_back(ev);
+        const size_t ev = 2 + 7 * (size_t)(bi % EV_RING);
+        if (bi >= EV_RING) {  // the slot's previous block: wait for it, keep its times
+            HIPCHK(hipEventSynchronize(g.events[ev + 2]));
+            add_times(bi - EV_RING);
+        }
+        filled[bi % EV_RING] = blk.n_bucket < blk.n_sieve;
         HIPCHK(hipEventRecord(g.events[ev], s));
         RCCHK(g.ss.sieve(blk, s, g.events[ev + 3], true, g.events[ev + 4], g.events[ev + 5],
                          g.events[ev + 6]));
@@ -1586,11 +1621,10 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
         if (y2 == b)
             HIPCHK(launch_interval_final(blk, g.iv_part.as<uint64_t>(), b, off, res, s));
         HIPCHK(hipEventRecord(g.events[ev + 2], s));
-        ev += 7;
         if (y2 == b)
             break;
     }
-    HIPCHK(hipEventRecord(g.events[ev], s));
+    HIPCHK(hipEventRecord(g.events[1], s));
     int64_t h[5];
     uint64_t entries = 0;
     HIPCHK(hipMemcpyAsync(h, res, sizeof h, hipMemcpyDeviceToHost, s));
@@ -1608,16 +1642,8 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
         m_ext[0] = h[1];
         m_ext[1] = h[3];
     }
-    double t_sieve = 0, t_prep = 0, t_red = 0, t_fill = 0, t_regroup = 0;
-    for (size_t m : marks) {
-        t_prep += elapsed(m, m + 3);
-        t_sieve += elapsed(m + 3, m + 1);
-        t_red += elapsed(m + 1, m + 2);
-    }
-    for (size_t f : fills) {
-        t_fill += elapsed(f, f + 1);
-        t_regroup += elapsed(f + 1, f + 2);
-    }
+    for (uint64_t bj = nblocks - nring; bj < nblocks; ++bj)
+        add_times(bj);
     for (double &v : g.stats)
         v = 0;
     g.stats[0] = (double)(b - start + 1);
@@ -1625,7 +1651,7 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
     g.stats[6] = t_sieve;
     g.stats[8] = t_prep;
     g.stats[9] = t_red;
-    g.stats[11] = elapsed(0, ev);
+    g.stats[11] = elapsed(0, 1);
     g.stats[13] = (double)nblocks;
     g.stats[16] = (double)entries;
     g.stats[17] = t_fill;
@@ -1714,6 +1740,10 @@ int mertens_set_param(const char *key, double value)
         if (!(value == 0.0 || value == 1.0))
             return MERTENS_EINVAL;
         g.tune.graph = value != 0.0;
+    } else if (!strcmp(key, "progress")) {
+        if (!(value >= 0.0 && value <= 1e12 && value == std::floor(value)))
+            return MERTENS_EINVAL;
+        g.tune.progress = (uint64_t)value;
     } else if (!strcmp(key, "wide_bits")) {
         if (!(value >= 33.0 && value <= 64.0 && value == std::floor(value)))
             return MERTENS_EINVAL;

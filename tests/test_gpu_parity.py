@@ -374,3 +374,12 @@ def test_table1_1e20_and_byproducts(mt):
     byp = mt.byproducts(0)
     assert [int(byp[c - 1]) for c in (10, 100, 1000, 10**4)] == [
         inputs.TABLE1[10**19], inputs.TABLE1[10**18], inputs.TABLE1[10**17], inputs.TABLE1[10**16]]
+
+
+@pytest.mark.skipif(os.environ.get("MERTENS_LONG") != "1",
+                    reason="about 8 minutes on one MI355X; set MERTENS_LONG=1 to run")
+def test_table1_1e21(mt):
+    # Table 1: M(10^21) = 3395895277, with M(10^20) among its byproducts
+    _reinit(mt, progress=2000)
+    assert int(mt.query_wide([10**21])[0]) == inputs.TABLE1[10**21]
+    assert int(mt.byproducts(0, 10)[9]) == inputs.TABLE1[10**20]
