@@ -17,6 +17,8 @@ Other workloads (``--workload``), reported separately:
            one-at-a-time FIFO server; p50/p99 latency and queries/s
   interval Section 6 localization: M(n) for every n of a 2^35-wide interval
            from the printed extreme on, and the extremes of M(n)/sqrt(n)
+  wide     M(10^20) past the 64-bit limit (about 100 s per step; use
+           --steps 1 --warmup 0)
 """
 from __future__ import annotations
 
@@ -352,6 +354,38 @@ def workload_interval(args, mt) -> dict:
     }
 
 
+def workload_wide(args, mt) -> dict:
+    """M(10^20) through mertens_query_wide (Table 1), one query per step."""
+    import torch
+    from paper_1108_0135_amd import inputs
+    n = 10**20
+    mt.init(0, 0)
+
+    def step():
+        got = int(mt.query_wide([n])[0])
+        if got != inputs.TABLE1[n]:
+            raise RuntimeError(f"wrong result M(1e20) = {got}")
+        return mt.stats()
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = [step() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    ms_step = 1000.0 * (time.perf_counter() - t0) / args.steps
+    st = sts[-1]
+    return {"metric": "sieved y/sec through update, M(10^20) past the 64-bit limit",
+            "value": st["sieved_y"] / (ms_step * 1e-3), "unit": "sieved y/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+            "data": "synthetic",
+            "config": {"workload": "single query n=1e20 (mertens_query_wide), automatic u",
+                       "u": st["u"], "blocks": st["blocks"], "parallelism": "1 GPU"},
+            "kernel_ms": {k: st[k] for k in ("ms_sieve", "ms_prep", "ms_update", "ms_finalize",
+                                             "ms_total")}}
+
+
 def workload_copy(args, mt) -> dict:
     """A plain device copy of known size (calibrates HBM byte counters)."""
     import torch
@@ -374,7 +408,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", choices=["default", "batched", "serving", "interval", "copy"],
+    ap.add_argument("--workload",
+                    choices=["default", "batched", "serving", "interval", "wide", "copy"],
                     default="default")
     ap.add_argument("--rate", type=float, default=10.0)
     ap.add_argument("--count", type=int, default=48)
@@ -403,6 +438,8 @@ def main() -> int:
             line = workload_interval(args, mt)
             if not args.no_cpu_baseline:
                 line["cpu_baseline"] = cpu_baseline_interval()
+        elif args.workload == "wide":
+            line = workload_wide(args, mt)
         elif args.workload == "copy":
             line = workload_copy(args, mt)
         else:

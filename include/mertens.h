@@ -175,7 +175,9 @@ int mertens_set_stream(void *hip_stream);
  *   "rl_fast"     1 (default): run-length quotients with m < 2^48 take the
  *                 test-free rounded-up fp64 floor; 0: always the tested path
  *   "progress"    k > 0: a query waits for every k-th block and prints
- *                 "mertens: block i of n updated" on stderr (default 0: off)
+ *                 "mertens: block i of n updated" on stderr, and for each
+ *                 update window of a block ("update_window") prints one line
+ *                 per window (default 0: off)
  *   "wide_bits"   x with floor(n/x) >= 2^wide_bits take the 128-bit wide
  *                 entries of mertens_query_wide (33..64; default 64, i.e.
  *                 only those past 64 bits; lower values route more x there,

@@ -856,6 +856,7 @@ struct Ctx {
     std::vector<int64_t> last_j;  // index in the batch, -1 for n = 0
     bool last_valid = false;
     double stats[20] = {0};
+    hipEvent_t progress_ev = nullptr;
     std::vector<hipEvent_t> events;
     Server srv;
 };
@@ -884,6 +885,9 @@ void free_all()
         (void)hipEventDestroy(e);
     g.sieved_ev.clear();
     g.updated_ev.clear();
+    if (g.progress_ev)
+        (void)hipEventDestroy(g.progress_ev);
+    g.progress_ev = nullptr;
     if (g.sieve_stream)
         (void)hipStreamDestroy(g.sieve_stream);
     g.sieve_stream = nullptr;
@@ -1063,11 +1067,21 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
         if (W && y1 < g.tune.window_ymax && y2 - y1 >= W &&
             (y2 - y1) / W < SieveState::MAX_WINDOWS) {
             uint32_t w = 0;
+            const uint64_t nw = (y2 - y1) / W + 1;
             for (uint64_t ua = y1; ua <= y2; ua += W, ++w) {
                 const BlockArgs bw = g.ss.window_of(b, ua, std::min(ua + W - 1, y2), w);
                 HIPCHK(launch_block_set(SieveState::params_of(bw),
                                         const_cast<BlockParams *>(bw.bp), s));
                 RCCHK(bt.update_block(bw, grid, s, w == 0 ? g.events[ev + 3] : nullptr));
+                if (g.tune.progress) {  // windows of a heavy block report one by one
+                    if (!g.progress_ev)
+                        HIPCHK(hipEventCreateWithFlags(&g.progress_ev, hipEventDisableTiming));
+                    HIPCHK(hipEventRecord(g.progress_ev, s));
+                    HIPCHK(hipEventSynchronize(g.progress_ev));
+                    fprintf(stderr, "mertens: block %llu window %u of %llu updated\n",
+                            (unsigned long long)bi, w + 1, (unsigned long long)nw);
+                    fflush(stderr);
+                }
             }
         } else {
             RCCHK(bt.update_block(b, grid, s, g.events[ev + 3]));

@@ -380,6 +380,7 @@ def test_table1_1e20_and_byproducts(mt):
                     reason="about 8 minutes on one MI355X; set MERTENS_LONG=1 to run")
 def test_table1_1e21(mt):
     # Table 1: M(10^21) = 3395895277, with M(10^20) among its byproducts
-    _reinit(mt, progress=2000)
+    # block 0 holds most of the update: it runs in 16 windows that report one by one
+    _reinit(mt, progress=2000, update_window=26)
     assert int(mt.query_wide([10**21])[0]) == inputs.TABLE1[10**21]
     assert int(mt.byproducts(0, 10)[9]) == inputs.TABLE1[10**20]
