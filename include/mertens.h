@@ -159,7 +159,8 @@ int mertens_set_stream(void *hip_stream);
  *   "kbal"        explicit-k tiles whose 8 x 8 walk would keep fewer than
  *                 1/kbal of its lanes busy take balanced per-lane runs of
  *                 their pairs instead (default 0: never)
- *   "waves_per_cu" persistent update grid size per compute unit (default 16)
+ *   "waves_per_cu" persistent update grid size per compute unit (default 12,
+ *                 the waves of three resident workgroups)
  *   "graph"       1: replay one captured hipGraph of the per-block kernel
  *                 sequence; 0: direct launches (default)
  *   "sieve_ahead" direct launches: most blocks sieved ahead of the update on

@@ -1790,8 +1790,10 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
 // Persistent update kernel of one block: wave w starts on item w and then
 // takes further items from a device counter until the block's items are
 // exhausted (a block with fewer items than waves costs no atomics beyond
-// one per item).
-__global__ __launch_bounds__(UPD_THREADS, 4) void k_update(QueryArgs q, BlockArgs b_in)
+// one per item).  Three workgroups per CU (12 waves, up to 168 VGPRs): the
+// run-length passes keep 16 x of quotient state per lane, which at four
+// workgroups (128 VGPRs) spilled to scratch.
+__global__ __launch_bounds__(UPD_THREADS, 3) void k_update(QueryArgs q, BlockArgs b_in)
 {
     // per wave: compacted run-length entries or explicit-k reciprocals
     static_assert(RL_ENT_CAP * 2 >= K2D_SUB * 8, "LDS slice too small");

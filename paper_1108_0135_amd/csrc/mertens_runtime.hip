@@ -162,7 +162,7 @@ uint64_t auto_u(long double total_n, double scale)
 struct Tuning {
     double u_scale = 0.5;  // automatic u = u_scale * (clustered sum of the batch's n)^(2/3)
     double beta = 0.25;
-    uint32_t ychunk = 16384, kchunk = 1024, waves_per_cu = 16;
+    uint32_t ychunk = 16384, kchunk = 1024, waves_per_cu = 12;  // 3 update workgroups per CU
     uint32_t kbal = 0;  // 0: every tile takes the 8 x 8 walk (measured best at 1e16)
     uint32_t sieve_ahead = 4;  // most record slots (blocks sieved ahead of the update)
     // blocks starting below window_ymax are updated in windows of
