@@ -346,7 +346,7 @@ def workload_interval(args, mt) -> dict:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u8",
         "data": "synthetic",
         "config": {"workload": f"interval [11609864264058592345, +2^35] from the printed M there, "
-                               f"primes to 3.4e9 (bucketed), y-blocks of 2^30",
+                               f"primes to 3.4e9 (bucketed), y-blocks of 2^31",
                    "blocks": st["blocks"], "parallelism": "1 GPU"},
         "kernel_ms": {k: avg(k) for k in ("ms_prep", "ms_sieve", "ms_update", "ms_bucket_fill",
                                           "ms_bucket_regroup", "ms_total")},

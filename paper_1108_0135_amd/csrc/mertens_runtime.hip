@@ -1575,8 +1575,10 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
     const uint64_t start = a - a % SEG;
     RCCHK(g.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(b), 1024)));
     RCCHK(g.ss.ensure_pattern());
+    // automatic blocks of up to 2^31 y: at high offsets every block visits every
+    // sieving prime (residues, buckets), so longer blocks cost less per value
     const uint64_t B =
-        g.block_req ? g.block_req : std::min<uint64_t>((b - start) / SEG * SEG + SEG, 1ull << 30);
+        g.block_req ? g.block_req : std::min<uint64_t>((b - start) / SEG * SEG + SEG, 1ull << 31);
     RCCHK(g.ss.ensure_blocks(B, 1));
     RCCHK(ensure(g.iv_part, (size_t)IV_WGS * 32));
     RCCHK(ensure(g.iv_small, 64));  // off at [0], results at [1..5]
