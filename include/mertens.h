@@ -263,6 +263,21 @@ int mertens_debug_div(const uint64_t *n, const uint64_t *d, size_t count,
                       uint64_t *q, int on_device);
 
 /*
+ * mertens_debug_wide -- the 128-bit quotient routines of mertens_query_wide on
+ * count arguments m = m_hi 2^64 + m_lo and divisors d, into q_hi 2^64 + q_lo:
+ *   op 0  floor(m/d), one quotient bit per step (any m, 1 <= d < 2^64)
+ *   op 1  floor(m/d) mod 2^64 (q_hi = 0) by three 32-bit digit steps, each
+ *         an fp64 estimate and one integer correction (m < 2^96, d < 2^32)
+ *   op 2  floor(m/d) (q_hi = 0) by an fp64 estimate and an exact 128-bit
+ *         check (floor(m/d) < 2^50)
+ * on_device = 0 runs the host build of the same routines, 1 runs them in a
+ * kernel.  Returns 0, MERTENS_EINVAL (null pointer, bad op, d = 0, or an
+ * argument outside the op's range), MERTENS_ENODEV, MERTENS_EIO.
+ */
+int mertens_debug_wide(const uint64_t *m_lo, const uint64_t *m_hi, const uint64_t *d,
+                       size_t count, uint64_t *q_lo, uint64_t *q_hi, int op, int on_device);
+
+/*
  * mertens_debug_mu -- mu(y) for y in [y1, y1 + count) from the device sieve
  * (Section 3, the 8-bit log-prime sieve with the corrected log rule) into
  * the host array mu (int8), and, if mert != NULL, the window partial sums

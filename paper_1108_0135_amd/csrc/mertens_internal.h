@@ -196,6 +196,12 @@ hipError_t launch_debug_div(const uint64_t *n, const uint64_t *d, uint64_t *q, s
 hipError_t launch_debug_mu(const BlockArgs &b, uint64_t y_first, uint32_t count, int8_t *mu,
                            int64_t *mert, hipStream_t s);
 
+// The 128-bit helpers of the wide entries on count arguments (out: two words
+// each; op as in mertens_debug_wide), on the device and in a host build.
+hipError_t launch_debug_wide(const uint64_t *mlo, const uint64_t *mhi, const uint64_t *d,
+                             uint64_t *out, size_t count, int op, hipStream_t s);
+void host_wide(int op, uint64_t mlo, uint64_t mhi, uint64_t d, uint64_t *qlo, uint64_t *qhi);
+
 // Host build of the device division routine (for tests without a GPU).
 void host_magic(uint32_t d, uint64_t *mul, uint32_t *sh1, uint32_t *sh2);
 uint64_t host_div(uint64_t n, uint64_t mul, uint32_t sh1, uint32_t sh2);

@@ -1015,19 +1015,19 @@ struct U128 {
     uint64_t lo, hi;
 };
 
-__device__ inline bool u128_less(U128 a, U128 b)
+__host__ __device__ inline bool u128_less(U128 a, U128 b)
 {
     return a.hi != b.hi ? a.hi < b.hi : a.lo < b.lo;
 }
 
-__device__ inline U128 mul64(uint64_t a, uint64_t b)
+__host__ __device__ inline U128 mul64(uint64_t a, uint64_t b)
 {
-    return U128{a * b, __umul64hi(a, b)};
+    return U128{a * b, mulhi64(a, b)};
 }
 
 // floor(a / d) for any a and d >= 1, one quotient bit per step (used once per
 // entry and block only).
-__device__ inline U128 udiv128_bits(U128 a, uint64_t d)
+__host__ __device__ inline U128 udiv128_bits(U128 a, uint64_t d)
 {
     U128 q{0, 0};
     uint64_t r = 0;
@@ -1048,7 +1048,7 @@ __device__ inline U128 udiv128_bits(U128 a, uint64_t d)
 
 // One digit step: floor(a / y) and a mod y for a < y 2^32, y < 2^32, from an
 // fp64 estimate (error below one) and one integer correction.
-__device__ inline uint64_t digit_div(uint64_t a, uint64_t y, double rcp, uint64_t &r)
+__host__ __device__ inline uint64_t digit_div(uint64_t a, uint64_t y, double rcp, uint64_t &r)
 {
     uint64_t q = (uint64_t)((double)a * rcp);
     r = a - q * y;
@@ -1063,7 +1063,7 @@ __device__ inline uint64_t digit_div(uint64_t a, uint64_t y, double rcp, uint64_
 }
 
 // floor(m / y) mod 2^64 for m < 2^96 and 1 <= y < 2^32.
-__device__ inline uint64_t wide_quot_low(U128 m, uint64_t y)
+__host__ __device__ inline uint64_t wide_quot_low(U128 m, uint64_t y)
 {
     const double rcp = 1.0 / (double)y;
     uint64_t r;
@@ -1075,7 +1075,7 @@ __device__ inline uint64_t wide_quot_low(U128 m, uint64_t y)
 
 // floor(m / k) for a quotient below 2^50: fp64 estimate, then the exact
 // 128-bit check either way.
-__device__ inline uint64_t wide_quot_small(U128 m, double md, uint64_t k)
+__host__ __device__ inline uint64_t wide_quot_small(U128 m, double md, uint64_t k)
 {
     uint64_t q = (uint64_t)(md / (double)k);
     if (u128_less(m, mul64(k, q)))
@@ -1083,6 +1083,49 @@ __device__ inline uint64_t wide_quot_small(U128 m, double md, uint64_t k)
     else if (!u128_less(m, mul64(k, q + 1)))
         ++q;
     return q;
+}
+
+// The wide helpers on one argument, for the diagnostic entry point:
+// op 0: floor(m/d) (128 bits, any d >= 1); op 1: floor(m/d) mod 2^64 by digit
+// steps (m < 2^96, d < 2^32); op 2: floor(m/d) by fp64 estimate and exact
+// check (quotient < 2^50).
+__host__ __device__ inline void wide_op(int op, uint64_t mlo, uint64_t mhi, uint64_t d,
+                                        uint64_t &qlo, uint64_t &qhi)
+{
+    const U128 m{mlo, mhi};
+    qhi = 0;
+    if (op == 0) {
+        const U128 q = udiv128_bits(m, d);
+        qlo = q.lo;
+        qhi = q.hi;
+    } else if (op == 1) {
+        qlo = wide_quot_low(m, d);
+    } else {
+        qlo = wide_quot_small(m, (double)mhi * 18446744073709551616.0 + (double)mlo, d);
+    }
+}
+
+void host_wide(int op, uint64_t mlo, uint64_t mhi, uint64_t d, uint64_t *qlo, uint64_t *qhi)
+{
+    wide_op(op, mlo, mhi, d, *qlo, *qhi);
+}
+
+__global__ void k_debug_wide(const uint64_t *mlo, const uint64_t *mhi, const uint64_t *d,
+                             uint64_t *out, size_t count, int op)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < count)
+        wide_op(op, mlo[i], mhi[i], d[i], out[2 * i], out[2 * i + 1]);
+}
+
+hipError_t launch_debug_wide(const uint64_t *mlo, const uint64_t *mhi, const uint64_t *d,
+                             uint64_t *out, size_t count, int op, hipStream_t s)
+{
+    if (count == 0)
+        return hipSuccess;
+    hipLaunchKernelGGL(k_debug_wide, dim3((uint32_t)((count + 255) / 256)), dim3(256), 0, s, mlo,
+                       mhi, d, out, count, op);
+    return hipGetLastError();
 }
 
 __global__ void k_wide_plan(QueryArgs q)

@@ -1911,6 +1911,71 @@ int mertens_debug_div(const uint64_t *n, const uint64_t *d, size_t count, uint64
     return rc;
 }
 
+int mertens_debug_wide(const uint64_t *m_lo, const uint64_t *m_hi, const uint64_t *d,
+                       size_t count, uint64_t *q_lo, uint64_t *q_hi, int op, int on_device)
+{
+    if (count == 0)
+        return 0;
+    if (!m_lo || !m_hi || !d || !q_lo || !q_hi || op < 0 || op > 2)
+        return MERTENS_EINVAL;
+    for (size_t i = 0; i < count; ++i) {
+        if (d[i] == 0)
+            return MERTENS_EINVAL;
+        const unsigned __int128 m = ((unsigned __int128)m_hi[i] << 64) | m_lo[i];
+        if (op == 1 && (d[i] >> 32 || m_hi[i] >> 32))
+            return MERTENS_EINVAL;
+        if (op == 2 && (m / d[i]) >> 50)
+            return MERTENS_EINVAL;
+    }
+    if (!on_device) {
+        for (size_t i = 0; i < count; ++i)
+            host_wide(op, m_lo[i], m_hi[i], d[i], &q_lo[i], &q_hi[i]);
+        return 0;
+    }
+    if (!g.ready)
+        return MERTENS_ENODEV;
+    DevBuf dml, dmh, dd, dq;
+    int rc = ensure(dml, count * 8);
+    if (!rc)
+        rc = ensure(dmh, count * 8);
+    if (!rc)
+        rc = ensure(dd, count * 8);
+    if (!rc)
+        rc = ensure(dq, count * 16);
+    std::vector<uint64_t> h;
+    if (!rc) {
+        hipError_t e = hipMemcpy(dml.p, m_lo, count * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(dmh.p, m_hi, count * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = hipMemcpy(dd.p, d, count * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess)
+            e = launch_debug_wide(dml.as<uint64_t>(), dmh.as<uint64_t>(), dd.as<uint64_t>(),
+                                  dq.as<uint64_t>(), count, op, g.stream);
+        if (e == hipSuccess)
+            e = hipStreamSynchronize(g.stream);
+        if (e == hipSuccess) {
+            h.resize(2 * count);
+            e = hipMemcpy(h.data(), dq.p, count * 16, hipMemcpyDeviceToHost);
+        }
+        if (e != hipSuccess) {
+            set_error("debug_wide", e, __FILE__, __LINE__);
+            rc = MERTENS_EIO;
+        }
+    }
+    dml.release();
+    dmh.release();
+    dd.release();
+    dq.release();
+    if (rc)
+        return rc;
+    for (size_t i = 0; i < count; ++i) {
+        q_lo[i] = h[2 * i];
+        q_hi[i] = h[2 * i + 1];
+    }
+    return 0;
+}
+
 int mertens_debug_mu(uint64_t y1, size_t count, int8_t *mu, int64_t *mert)
 {
     if (count == 0)

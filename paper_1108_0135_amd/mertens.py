@@ -46,6 +46,8 @@ _sig = {
                          ctypes.c_int),
     "mertens_debug_div": ([_P(_u64), _P(_u64), _sz, _P(_u64), ctypes.c_int], ctypes.c_int),
     "mertens_debug_mu": ([_u64, _sz, _P(ctypes.c_int8), _P(_i64)], ctypes.c_int),
+    "mertens_debug_wide": ([_P(_u64), _P(_u64), _P(_u64), _sz, _P(_u64), _P(_u64), ctypes.c_int,
+                            ctypes.c_int], ctypes.c_int),
 }
 for _name, (_args, _ret) in _sig.items():
     _f = getattr(_lib, _name)
@@ -180,6 +182,18 @@ def debug_div(n, d, on_device: bool) -> np.ndarray:
     _check(_lib.mertens_debug_div(_u64p(na), _u64p(da), na.size, _u64p(q), int(on_device)),
            "mertens_debug_div")
     return q
+
+
+def debug_wide(ms, ds, op: int, on_device: bool) -> list:
+    """The wide-entry quotient routines on Python ints m (< 2^128) and d (< 2^64)."""
+    lo = np.array([int(m) & (2**64 - 1) for m in ms], dtype=np.uint64)
+    hi = np.array([int(m) >> 64 for m in ms], dtype=np.uint64)
+    d = np.array([int(v) for v in ds], dtype=np.uint64)
+    qlo = np.zeros(len(lo), dtype=np.uint64)
+    qhi = np.zeros(len(lo), dtype=np.uint64)
+    _check(_lib.mertens_debug_wide(_u64p(lo), _u64p(hi), _u64p(d), len(lo), _u64p(qlo), _u64p(qhi),
+                                   op, int(on_device)), "mertens_debug_wide")
+    return [(int(h) << 64) | int(l) for l, h in zip(qlo, qhi)]
 
 
 def debug_mu(y1: int, count: int, with_sums: bool = True):

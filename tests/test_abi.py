@@ -105,3 +105,64 @@ def test_gm_division_host_exact():
     q = mt.debug_div(n, d, on_device=False)
     ref = np.array([int(a) // int(b) for a, b in zip(n, d)], dtype=np.uint64)
     assert np.array_equal(q, ref)
+
+
+def _wide_cases(rng, op: int, count: int = 4000):
+    """(m, d) pairs for each routine of mertens_debug_wide, with the edges of
+    its range: random bit lengths, d = 1 and the largest d, m = 0, the largest
+    m, and m = q d + r with r in {0, 1, d - 1} (quotients that sit exactly on,
+    just above and just below an integer boundary)."""
+    def rnd(bits):
+        b = int(rng.integers(0, bits + 1))
+        return int.from_bytes(rng.bytes(16), "little") >> (128 - b) if b else 0
+    ms, ds = [], []
+    mbits, dbits = {0: (128, 64), 1: (96, 32), 2: (114, 64)}[op]
+    for _ in range(count):
+        d = max(1, rnd(dbits))
+        if op == 2:
+            q = rnd(50) if rng.random() < 0.9 else (1 << 50) - 1
+            if q * d >= 1 << 128:
+                d = max(1, ((1 << 128) - 1) // max(q, 1))
+            r = [0, 1, d - 1, rnd(64) % d][int(rng.integers(0, 4))] if d > 1 else 0
+            m = q * d + r
+        else:
+            m = rnd(mbits)
+            if rng.random() < 0.3:  # near a multiple of d
+                q = m // d
+                m = min(q * d + [0, 1, d - 1][int(rng.integers(0, 3))], (1 << mbits) - 1)
+        ms.append(m)
+        ds.append(d)
+    top = (1 << mbits) - 1
+    ms += [0, top, top, 1 << 64 if mbits > 64 else 1, top]
+    ds += [1, 1, (1 << dbits) - 1, 3, 2] if op != 2 else [1, 1 << 20, 1 << 63, 3, 1 << 62]
+    if op == 2:  # keep every quotient below 2^50
+        ms[-4:] = [(1 << 70) - 1, (1 << 113) - 1, 5, (1 << 111) + 7]
+    return ms, ds
+
+
+def _wide_expect(op, ms, ds):
+    return [m // d if op != 1 else (m // d) % (1 << 64) for m, d in zip(ms, ds)]
+
+
+@pytest.mark.parametrize("op", [0, 1, 2])
+def test_wide_division_host(op):
+    # host build of the 128-bit quotient routines against Python integers
+    rng = np.random.default_rng(30 + op)
+    ms, ds = _wide_cases(rng, op)
+    assert mt.debug_wide(ms, ds, op, on_device=False) == _wide_expect(op, ms, ds)
+
+
+def test_wide_division_ranges():
+    lib = mt.raw()
+    one = np.array([1], dtype=np.uint64)
+    zero = np.array([0], dtype=np.uint64)
+    big = np.array([1 << 32], dtype=np.uint64)
+    q = np.zeros(1, dtype=np.uint64)
+    q2 = np.zeros(1, dtype=np.uint64)
+    f = lambda lo, hi, d, op: lib.mertens_debug_wide(mt._u64p(lo), mt._u64p(hi), mt._u64p(d), 1,
+                                                     mt._u64p(q), mt._u64p(q2), op, 0)
+    assert f(one, zero, zero, 0) == mt.EINVAL      # d = 0
+    assert f(one, zero, big, 1) == mt.EINVAL       # digit steps need d < 2^32
+    assert f(one, big, one, 1) == mt.EINVAL        # ... and m < 2^96
+    assert f(one, one, one, 2) == mt.EINVAL        # quotient 2^64 + 1 >= 2^50
+    assert f(one, zero, one, 3) == mt.EINVAL       # no such op

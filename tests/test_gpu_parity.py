@@ -338,6 +338,15 @@ def test_interval_section6_extreme_window(mt):
 
 # ------------------------------------------------------------------ arguments past 2^64
 
+@pytest.mark.parametrize("op", [0, 1, 2])
+def test_wide_division_device(mt, op):
+    # the 128-bit quotient routines in a kernel, against Python integers
+    from tests.test_abi import _wide_cases, _wide_expect
+    rng = np.random.default_rng(40 + op)
+    ms, ds = _wide_cases(rng, op, count=20000)
+    assert mt.debug_wide(ms, ds, op, on_device=True) == _wide_expect(op, ms, ds)
+
+
 def test_wide_entries_vs_golden(mt):
     # every x with floor(n/x) >= 2^33 goes through the 128-bit wide entries
     # (the path arguments past 2^64 take), at sizes the oracle reaches
