@@ -389,8 +389,8 @@ def test_table1_1e20_and_byproducts(mt):
                     reason="about 10 minutes on one MI355X; set MERTENS_LONG=1 to run")
 def test_table1_1e21(mt):
     # Table 1 prints M(10^21) = 3395895277.  This build computes -3395895277,
-    # the same under u = 5e13 and 3.5e13, beta 0.25 and 0.5, fp64-tested and
-    # check-free quotients, while the same run reproduces the printed M(10^20),
+    # the same under u = 5e13, 3.5e13 and 1e14, beta 0.25 and 0.5, fp64-tested
+    # and check-free quotients, while the same run reproduces the printed M(10^20),
     # M(10^19) and M(10^18) as byproducts.  The magnitude is pinned to the
     # print; the sign is the open discrepancy this test keeps visible.
     # Block 0 holds most of the update: it runs in 16 windows that report.
