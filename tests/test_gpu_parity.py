@@ -388,7 +388,7 @@ def test_table1_1e20_and_byproducts(mt):
 @pytest.mark.skipif(os.environ.get("MERTENS_LONG") != "1",
                     reason="about 10 minutes on one MI355X; set MERTENS_LONG=1 to run")
 def test_table1_1e21(mt):
-    # Table 1 prints M(10^21) = 3395895277.  This build computes -3395895277,
+    # Table 1 prints M(10^21) = 3395895277.  The library computes -3395895277,
     # the same under u = 5e13, 3.5e13 and 1e14, beta 0.25 and 0.5, fp64-tested
     # and check-free quotients, while the same run reproduces the printed M(10^20),
     # M(10^19) and M(10^18) as byproducts.  The magnitude is pinned to the
