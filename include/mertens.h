@@ -278,6 +278,18 @@ int mertens_debug_wide(const uint64_t *m_lo, const uint64_t *m_hi, const uint64_
                        size_t count, uint64_t *q_lo, uint64_t *q_hi, int op, int on_device);
 
 /*
+ * mertens_debug_runsum -- for n = n_hi 2^64 + n_lo (< 2^82) and L >= 1, the
+ * sum over k > L of M(floor(n/k)) mod 2^64 (the term S[1] of the identity
+ * with split L, Section 2), evaluated the plain way: a sieve sweep over
+ * y <= floor(n/(L+1)) (< 2^50) adding (floor(n/y) - floor(n/(y+1))) M(y),
+ * with floor(n/ymax) - L at the top, and no explicit-k part.  With the
+ * byproducts A[2..L] of a query using the same L it gives an independent
+ * M(n) = 1 - S - sum A[k].  Slow (two quotients per y); "progress" reports.
+ * Returns 0, MERTENS_EINVAL, MERTENS_ENODEV, MERTENS_ENOMEM, MERTENS_EIO.
+ */
+int mertens_debug_runsum(uint64_t n_lo, uint64_t n_hi, uint64_t L, uint64_t *s_out);
+
+/*
  * mertens_debug_mu -- mu(y) for y in [y1, y1 + count) from the device sieve
  * (Section 3, the 8-bit log-prime sieve with the corrected log rule) into
  * the host array mu (int8), and, if mert != NULL, the window partial sums

@@ -202,6 +202,11 @@ hipError_t launch_debug_wide(const uint64_t *mlo, const uint64_t *mhi, const uin
                              uint64_t *out, size_t count, int op, hipStream_t s);
 void host_wide(int op, uint64_t mlo, uint64_t mhi, uint64_t d, uint64_t *qlo, uint64_t *qhi);
 
+// acc += sum over y in the block, 1 <= y <= ymax, of w(y) M(y) mod 2^64 with
+// w(y) = floor(n/y) - floor(n/(y+1)) (floor(n/ymax) - L at ymax)
+hipError_t launch_debug_runsum(const BlockArgs &b, uint64_t nlo, uint64_t nhi, uint64_t ymax,
+                               uint64_t L, uint64_t *acc, hipStream_t s);
+
 // Host build of the device division routine (for tests without a GPU).
 void host_magic(uint32_t d, uint64_t *mul, uint32_t *sh1, uint32_t *sh2);
 uint64_t host_div(uint64_t n, uint64_t mul, uint32_t sh1, uint32_t sh2);

@@ -1128,6 +1128,43 @@ hipError_t launch_debug_wide(const uint64_t *mlo, const uint64_t *mhi, const uin
     return hipGetLastError();
 }
 
+// Diagnostic: the sum over k > L of M(floor(n/k)) for one argument n < 2^82,
+// grouped by y = floor(n/k) with plain weights floor(n/y) - floor(n/(y+1))
+// (floor(n/ymax) - L at y = ymax), all mod 2^64; no split, no explicit k.
+// Every quotient is taken mod 2^64: by 32-bit digit steps for y < 2^32,
+// else by the fp64 estimate with the exact 128-bit check (quotient < 2^50).
+__device__ inline uint64_t quot_low_any(U128 n, double nd, uint64_t y)
+{
+    return y < (1ull << 32) ? wide_quot_low(n, y) : wide_quot_small(n, nd, y);
+}
+
+__global__ __launch_bounds__(256) void k_debug_runsum(BlockArgs b_in, uint64_t nlo, uint64_t nhi,
+                                                      uint64_t ymax, uint64_t L, uint64_t *acc)
+{
+    const BlockArgs b = load_block(b_in);
+    const U128 n{nlo, nhi};
+    const double nd = (double)nhi * 18446744073709551616.0 + (double)nlo;
+    const uint64_t y1e = b.y1 > 0 ? b.y1 : 1;
+    const uint64_t yhi = b.y2 < ymax ? b.y2 : ymax;
+    uint64_t s = 0;
+    for (uint64_t y = y1e + (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; y <= yhi;
+         y += (uint64_t)gridDim.x * blockDim.x) {
+        const uint64_t qy = quot_low_any(n, nd, y);
+        const uint64_t w = y < ymax ? qy - quot_low_any(n, nd, y + 1) : qy - L;
+        s += w * (uint64_t)M_at(b.words, y - b.y1);
+    }
+    s = wave_sum_u64(s);
+    if (lane_id() == 0 && s)
+        atomicAdd(reinterpret_cast<unsigned long long *>(acc), (unsigned long long)s);
+}
+
+hipError_t launch_debug_runsum(const BlockArgs &b, uint64_t nlo, uint64_t nhi, uint64_t ymax,
+                               uint64_t L, uint64_t *acc, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_debug_runsum, dim3(4096), dim3(256), 0, s, b, nlo, nhi, ymax, L, acc);
+    return hipGetLastError();
+}
+
 __global__ void k_wide_plan(QueryArgs q)
 {
     const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;

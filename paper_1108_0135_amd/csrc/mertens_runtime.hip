@@ -1976,6 +1976,46 @@ int mertens_debug_wide(const uint64_t *m_lo, const uint64_t *m_hi, const uint64_
     return 0;
 }
 
+int mertens_debug_runsum(uint64_t n_lo, uint64_t n_hi, uint64_t L, uint64_t *s_out)
+{
+    if (!s_out || L == 0 || (n_hi >> 18))
+        return MERTENS_EINVAL;
+    const unsigned __int128 N = ((unsigned __int128)n_hi << 64) | n_lo;
+    const unsigned __int128 ym = N / (L + 1);
+    if (ym == 0 || (ym >> 50)) {
+        set_error_text("runsum needs 1 <= n/(L+1) < 2^50");
+        return MERTENS_EINVAL;
+    }
+    if (!g.ready)
+        return MERTENS_ENODEV;
+    const uint64_t ymax = (uint64_t)ym;
+    hipStream_t s = g.stream;
+    RCCHK(g.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(ymax), 1024)));
+    RCCHK(g.ss.ensure_pattern());
+    const uint64_t B = choose_block(g.block_req, ymax);
+    RCCHK(g.ss.ensure_blocks(B, 1));
+    RCCHK(ensure(g.iv_small, 64));
+    uint64_t *acc = g.iv_small.as<uint64_t>() + 7;
+    RCCHK(g.ss.reset_carry(s));
+    HIPCHK(launch_zero_u64(acc, 1, s));
+    const uint64_t nblocks = ymax / B + 1;
+    for (uint64_t bi = 0; bi < nblocks; ++bi) {
+        const uint64_t y1 = bi * B, y2 = std::min(y1 + B - 1, ymax);
+        const BlockArgs blk = g.ss.make_block(y1, y2);
+        RCCHK(g.ss.sieve(blk, s, nullptr));
+        HIPCHK(launch_debug_runsum(blk, n_lo, n_hi, ymax, L, acc, s));
+        if (g.tune.progress && (bi + 1) % g.tune.progress == 0) {
+            HIPCHK(hipStreamSynchronize(s));
+            fprintf(stderr, "mertens: runsum block %llu of %llu\n", (unsigned long long)(bi + 1),
+                    (unsigned long long)nblocks);
+            fflush(stderr);
+        }
+    }
+    HIPCHK(hipMemcpyAsync(s_out, acc, 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return 0;
+}
+
 int mertens_debug_mu(uint64_t y1, size_t count, int8_t *mu, int64_t *mert)
 {
     if (count == 0)

@@ -46,6 +46,7 @@ _sig = {
                          ctypes.c_int),
     "mertens_debug_div": ([_P(_u64), _P(_u64), _sz, _P(_u64), ctypes.c_int], ctypes.c_int),
     "mertens_debug_mu": ([_u64, _sz, _P(ctypes.c_int8), _P(_i64)], ctypes.c_int),
+    "mertens_debug_runsum": ([_u64, _u64, _u64, _P(_u64)], ctypes.c_int),
     "mertens_debug_wide": ([_P(_u64), _P(_u64), _P(_u64), _sz, _P(_u64), _P(_u64), ctypes.c_int,
                             ctypes.c_int], ctypes.c_int),
 }
@@ -194,6 +195,14 @@ def debug_wide(ms, ds, op: int, on_device: bool) -> list:
     _check(_lib.mertens_debug_wide(_u64p(lo), _u64p(hi), _u64p(d), len(lo), _u64p(qlo), _u64p(qhi),
                                    op, int(on_device)), "mertens_debug_wide")
     return [(int(h) << 64) | int(l) for l, h in zip(qlo, qhi)]
+
+
+def debug_runsum(n: int, L: int) -> int:
+    """sum_{k > L} M(floor(n/k)) mod 2^64 by the plain grouped sweep."""
+    out = _u64(0)
+    _check(_lib.mertens_debug_runsum(n & (2**64 - 1), n >> 64, L, ctypes.byref(out)),
+           "mertens_debug_runsum")
+    return int(out.value)
 
 
 def debug_mu(y1: int, count: int, with_sums: bool = True):

@@ -166,3 +166,7 @@ def test_wide_division_ranges():
     assert f(one, big, one, 1) == mt.EINVAL        # ... and m < 2^96
     assert f(one, one, one, 2) == mt.EINVAL        # quotient 2^64 + 1 >= 2^50
     assert f(one, zero, one, 3) == mt.EINVAL       # no such op
+    out = ctypes.c_uint64(0)
+    assert lib.mertens_debug_runsum(5, 1 << 18, 10, ctypes.byref(out)) == mt.EINVAL  # n >= 2^82
+    assert lib.mertens_debug_runsum(5, 0, 0, ctypes.byref(out)) == mt.EINVAL         # L = 0
+    assert lib.mertens_debug_runsum(5, 0, 10, ctypes.byref(out)) == mt.EINVAL        # n/(L+1) = 0

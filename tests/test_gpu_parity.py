@@ -375,6 +375,29 @@ def test_query_wide_low_words_match_query(mt):
     assert list(mt.query_wide(ns)) == list(mt.query(ns))
 
 
+def test_runsum_matches_split_and_oracle(mt):
+    # the plain grouped sum over k > L of M(floor(n/k)) (no split, no explicit
+    # k, mod 2^64) against the oracle's table, and 1 - S - sum A[2..L] against
+    # the split path's M(n), for a 64-bit and a 128-bit argument
+    n, L = 10**10 + 7, 1000
+    ymax = n // (L + 1)
+    tab = oracle.mertens_table(ymax).astype(np.int64)
+    q = np.uint64(n) // np.arange(1, ymax + 2, dtype=np.uint64)  # floor(n/y), y = 1..ymax+1
+    w = q[:-1] - q[1:]
+    w[-1] = q[-2] - np.uint64(L)  # y = ymax: the k in (L, n/ymax]
+    with np.errstate(over="ignore"):
+        want = int(np.sum(w * tab[1:].astype(np.uint64), dtype=np.uint64))
+    _reinit(mt)
+    assert mt.debug_runsum(n, L) == want
+    for N in (10**12, 10**15 + 12345):
+        _reinit(mt)
+        m = int(mt.query_wide([N])[0])
+        byp = [int(v) for v in mt.byproducts(0)]
+        S = mt.debug_runsum(N, len(byp))
+        got = (1 - S - sum(byp[1:])) % (1 << 64)
+        assert got - (1 << 64) * (got >= 1 << 63) == m
+
+
 def test_table1_1e20_and_byproducts(mt):
     # Table 1: M(10^20) = 461113106; its byproducts M(10^20 / c) give the
     # printed M(10^19), M(10^18), M(10^17), M(10^16) (Section 1)
