@@ -413,9 +413,10 @@ def test_table1_1e20_and_byproducts(mt):
 def test_table1_1e21(mt):
     # Table 1 prints M(10^21) = 3395895277.  The library computes -3395895277,
     # the same under u = 5e13, 3.5e13 and 1e14, beta 0.25 and 0.5, fp64-tested
-    # and check-free quotients, while the same run reproduces the printed M(10^20),
-    # M(10^19) and M(10^18) as byproducts.  The magnitude is pinned to the
-    # print; the sign is the open discrepancy this test keeps visible.
+    # and check-free quotients, and with the k > L term evaluated the plain way
+    # (mertens_debug_runsum), while the same run reproduces the printed
+    # M(10^20), M(10^19) and M(10^18) as byproducts.  The magnitude is pinned
+    # to the print; the sign difference stays visible here.
     # Block 0 holds most of the update: it runs in 16 windows that report.
     _reinit(mt, progress=2000, update_window=26)
     got = int(mt.query_wide([10**21])[0])
