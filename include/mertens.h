@@ -237,8 +237,9 @@ const char *mertens_last_error(void);
  *           cap >= b - a + 1 and b - a + 1 <= 2^28.
  * The sweep sieves mu over [a - (a mod 2^17), b] in blocks (the init block
  * size, or automatically up to 2^31 y; device primes up to ceil(sqrt(b)),
- * the ones above 2^17 through per-segment buckets), runs
- * the M(y) prefix from zero, and shifts it by M(a) minus the prefix at a.
+ * those above 2^17 through per-segment buckets once there are "bucket_min"
+ * of them), runs the M(y) prefix from zero, and shifts it by M(a) minus the
+ * prefix at a.
  * mertens_stats afterwards: sieved_y, blocks, ms_sieve (the sieve kernel
  * with its fused prefix), ms_prep (block set-up, square and prime buckets),
  * ms_update (the interval reductions), ms_total, sieve_launches and slots
