@@ -17,8 +17,8 @@ Other workloads (``--workload``), reported separately:
            one-at-a-time FIFO server; p50/p99 latency and queries/s
   interval Section 6 localization: M(n) for every n of a 2^35-wide interval
            from the printed extreme on, and the extremes of M(n)/sqrt(n)
-  wide     M(10^20) past the 64-bit limit (about 100 s per step; use
-           --steps 1 --warmup 0)
+  wide     M(10^20) past the 64-bit limit (about 100 s per step; one timed
+           step and no warmup unless asked)
 """
 from __future__ import annotations
 
@@ -406,8 +406,10 @@ def workload_copy(args, mt) -> dict:
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed steps (default 5; 1 for the wide workload)")
+    ap.add_argument("--warmup", type=int, default=None,
+                    help="untimed warmup steps (default 1; 0 for the wide workload)")
     ap.add_argument("--workload",
                     choices=["default", "batched", "serving", "interval", "wide", "copy"],
                     default="default")
@@ -418,6 +420,11 @@ def main() -> int:
     ap.add_argument("--in-turn", action="store_true",
                     help="sieve strictly in turn with the update (for per-kernel profiles)")
     args = ap.parse_args()
+    long_steps = args.workload == "wide"  # about 100 s per step
+    if args.steps is None:
+        args.steps = 1 if long_steps else 5
+    if args.warmup is None:
+        args.warmup = 0 if long_steps else 1
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the sweep has no multi-GPU path",
               file=sys.stderr)
