@@ -291,6 +291,14 @@ int mertens_debug_wide(const uint64_t *m_lo, const uint64_t *m_hi, const uint64_
 int mertens_debug_runsum(uint64_t n_lo, uint64_t n_hi, uint64_t L, uint64_t *s_out);
 
 /*
+ * mertens_debug_primes -- the host prime table the sieve uploads: the count,
+ * the largest and the sum of the primes p with 5 <= p <= limit (limit <=
+ * 2^32; segmented sieve of Eratosthenes over odd numbers).  Needs no GPU.
+ * Returns 0 or MERTENS_EINVAL.
+ */
+int mertens_debug_primes(uint64_t limit, uint64_t *count, uint64_t *last, uint64_t *sum);
+
+/*
  * mertens_debug_mu -- mu(y) for y in [y1, y1 + count) from the device sieve
  * (Section 3, the 8-bit log-prime sieve with the corrected log rule) into
  * the host array mu (int8), and, if mert != NULL, the window partial sums

@@ -180,6 +180,43 @@ struct Tuning {
     bool graph = false;  // replay one captured hipGraph per block
 };
 
+// Primes p in [5, limit] (limit <= 2^32) into pr, ascending: segmented
+// Eratosthenes over odd numbers, 2^19 of them per segment, crossed off by the
+// base primes up to sqrt(limit).
+void host_primes(uint64_t limit, std::vector<uint32_t> &pr)
+{
+    pr.clear();
+    const uint64_t root = isqrt_host(limit);
+    std::vector<uint8_t> bc(root / 2 + 1, 0);  // bc[i] <=> 2i+1 composite, 2i+1 <= root
+    std::vector<uint32_t> base;
+    for (uint64_t i = 3; i <= root; i += 2)
+        if (!bc[i / 2]) {
+            base.push_back((uint32_t)i);
+            for (uint64_t j = i * i; j <= root; j += 2 * i)
+                bc[j / 2] = 1;
+        }
+    pr.reserve((size_t)(1.1 * (double)limit / std::max(1.0, std::log((double)limit))) + 16);
+    constexpr uint64_t SPAN = 1ull << 19;  // odd numbers per segment
+    std::vector<uint8_t> comp(SPAN);
+    for (uint64_t lo = 1; lo <= limit; lo += 2 * SPAN) {  // odd v in [lo, lo + 2 SPAN)
+        std::fill(comp.begin(), comp.end(), 0);
+        const uint64_t hi = std::min(lo + 2 * SPAN - 1, limit);
+        for (uint32_t q : base) {
+            const uint64_t qq = (uint64_t)q * q;
+            if (qq > hi)
+                break;
+            uint64_t f = std::max(qq, (lo + q - 1) / q * q);
+            if (f % 2 == 0)
+                f += q;
+            for (uint64_t v = f; v <= hi; v += 2 * q)
+                comp[(v - lo) / 2] = 1;
+        }
+        for (uint64_t v = std::max<uint64_t>(lo, 5); v <= hi; v += 2)
+            if (!comp[(v - lo) / 2])
+                pr.push_back((uint32_t)v);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Device tables and block buffers of one sweep engine.
 // ---------------------------------------------------------------------------
@@ -205,45 +242,16 @@ struct SieveState {
         have_pattern = false;
     }
 
-    // Sieving primes p in [5, limit] (segmented Eratosthenes over odd
-    // numbers, 2^19 of them per segment, from the base primes up to
-    // sqrt(limit)) and their device copy as {p, residue} pairs.  Grows only.
+    // Sieving primes p in [5, limit] (host_primes) and their device copy as
+    // {p, residue} pairs.  Grows only, by at least a quarter at a time.
     int ensure_primes(uint64_t limit)
     {
         if (limit <= psieve)
             return 0;
         if (psieve)  // grow by at least a quarter, so rising limits re-sieve rarely
             limit = std::max(limit, std::min<uint64_t>(psieve + psieve / 4, 1ull << 32));
-        const uint64_t root = isqrt_host(limit);
-        std::vector<uint8_t> bc(root / 2 + 1, 0);  // bc[i] <=> 2i+1 composite, 2i+1 <= root
-        std::vector<uint32_t> base;
-        for (uint64_t i = 3; i <= root; i += 2)
-            if (!bc[i / 2]) {
-                base.push_back((uint32_t)i);
-                for (uint64_t j = i * i; j <= root; j += 2 * i)
-                    bc[j / 2] = 1;
-            }
         std::vector<uint32_t> pr;
-        pr.reserve((size_t)(1.1 * (double)limit / std::max(1.0, std::log((double)limit))) + 16);
-        constexpr uint64_t SPAN = 1ull << 19;  // odd numbers per segment
-        std::vector<uint8_t> comp(SPAN);
-        for (uint64_t lo = 1; lo <= limit; lo += 2 * SPAN) {  // odd v in [lo, lo + 2 SPAN)
-            std::fill(comp.begin(), comp.end(), 0);
-            const uint64_t hi = std::min(lo + 2 * SPAN - 1, limit);
-            for (uint32_t q : base) {
-                const uint64_t qq = (uint64_t)q * q;
-                if (qq > hi)
-                    break;
-                uint64_t f = std::max(qq, (lo + q - 1) / q * q);
-                if (f % 2 == 0)
-                    f += q;
-                for (uint64_t v = f; v <= hi; v += 2 * q)
-                    comp[(v - lo) / 2] = 1;
-            }
-            for (uint64_t v = std::max<uint64_t>(lo, 5); v <= hi; v += 2)
-                if (!comp[(v - lo) / 2])
-                    pr.push_back((uint32_t)v);
-        }
+        host_primes(limit, pr);
         const size_t np = pr.size();
         std::vector<uint32_t> pairs(2 * np, 0u);
         for (size_t i = 0; i < np; ++i)
@@ -2013,6 +2021,21 @@ int mertens_debug_runsum(uint64_t n_lo, uint64_t n_hi, uint64_t L, uint64_t *s_o
     }
     HIPCHK(hipMemcpyAsync(s_out, acc, 8, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
+    return 0;
+}
+
+int mertens_debug_primes(uint64_t limit, uint64_t *count, uint64_t *last, uint64_t *sum)
+{
+    if (!count || !last || !sum || limit > (1ull << 32))
+        return MERTENS_EINVAL;
+    std::vector<uint32_t> pr;
+    host_primes(limit, pr);
+    *count = pr.size();
+    *last = pr.empty() ? 0 : pr.back();
+    uint64_t t = 0;
+    for (uint32_t p : pr)
+        t += p;
+    *sum = t;
     return 0;
 }
 

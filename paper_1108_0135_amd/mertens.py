@@ -47,6 +47,7 @@ _sig = {
     "mertens_debug_div": ([_P(_u64), _P(_u64), _sz, _P(_u64), ctypes.c_int], ctypes.c_int),
     "mertens_debug_mu": ([_u64, _sz, _P(ctypes.c_int8), _P(_i64)], ctypes.c_int),
     "mertens_debug_runsum": ([_u64, _u64, _u64, _P(_u64)], ctypes.c_int),
+    "mertens_debug_primes": ([_u64, _P(_u64), _P(_u64), _P(_u64)], ctypes.c_int),
     "mertens_debug_wide": ([_P(_u64), _P(_u64), _P(_u64), _sz, _P(_u64), _P(_u64), ctypes.c_int,
                             ctypes.c_int], ctypes.c_int),
 }
@@ -203,6 +204,14 @@ def debug_runsum(n: int, L: int) -> int:
     _check(_lib.mertens_debug_runsum(n & (2**64 - 1), n >> 64, L, ctypes.byref(out)),
            "mertens_debug_runsum")
     return int(out.value)
+
+
+def debug_primes(limit: int):
+    """(count, largest, sum) of the primes 5 <= p <= limit of the host table."""
+    c, l, t = _u64(0), _u64(0), _u64(0)
+    _check(_lib.mertens_debug_primes(limit, ctypes.byref(c), ctypes.byref(l), ctypes.byref(t)),
+           "mertens_debug_primes")
+    return int(c.value), int(l.value), int(t.value)
 
 
 def debug_mu(y1: int, count: int, with_sums: bool = True):

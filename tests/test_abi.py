@@ -170,3 +170,26 @@ def test_wide_division_ranges():
     assert lib.mertens_debug_runsum(5, 1 << 18, 10, ctypes.byref(out)) == mt.EINVAL  # n >= 2^82
     assert lib.mertens_debug_runsum(5, 0, 0, ctypes.byref(out)) == mt.EINVAL         # L = 0
     assert lib.mertens_debug_runsum(5, 0, 10, ctypes.byref(out)) == mt.EINVAL        # n/(L+1) = 0
+
+
+def test_host_prime_table():
+    # the sieving primes (5 <= p <= limit) of the host table against prime
+    # counts: pi(10^6) = 78498, pi(10^9) = 50847534, pi(2^32) = 203280221, and
+    # against a direct numpy sieve on small limits (count, largest, sum)
+    for limit in (4, 5, 6, 1000, 2**19, 2**20 + 3, 10**6):
+        s = np.ones(limit + 1, dtype=bool)
+        s[:2] = False
+        for i in range(2, int(limit ** 0.5) + 1):
+            if s[i]:
+                s[i * i::i] = False
+        ps = np.nonzero(s)[0]
+        ps = ps[ps >= 5]
+        want = (len(ps), int(ps[-1]) if len(ps) else 0, int(ps.sum()))
+        assert mt.debug_primes(limit) == want, limit
+    assert mt.debug_primes(10**9)[0] == 50847534 - 2
+    count, last, _ = mt.debug_primes(2**32)
+    assert (count, last) == (203280221 - 2, 4294967291)
+    lib = mt.raw()
+    c = ctypes.c_uint64(0)
+    assert lib.mertens_debug_primes(2**32 + 1, ctypes.byref(c), ctypes.byref(c),
+                                    ctypes.byref(c)) == mt.EINVAL
