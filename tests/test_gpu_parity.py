@@ -57,6 +57,21 @@ def test_sieve_mu_and_M_from_zero(mt):
     assert np.array_equal(sums, oracle.mertens_table(N).astype(np.int64))
 
 
+@pytest.mark.skipif(os.environ.get("MERTENS_LONG") != "1",
+                    reason="a few minutes (oracle sieve of 10^10 values); set MERTENS_LONG=1 to run")
+def test_sieve_mu_exhaustive_to_1e10(mt):
+    # every mu(y), y in [0, 10^10], from the device sieve against the oracle,
+    # in chunks of 2^26 values (sums of each chunk checked too)
+    _reinit(mt)
+    N, step = 10**10, 1 << 26
+    for y1 in range(0, N + 1, step):
+        cnt = min(step, N + 1 - y1)
+        mu, sums = mt.debug_mu(y1, cnt)
+        ref = oracle.mu_range(y1, y1 + cnt - 1)
+        assert np.array_equal(mu, ref), y1
+        assert int(sums[-1]) == int(ref.astype(np.int64).sum()), y1
+
+
 @pytest.mark.parametrize("y1", [10**9 - 70_000, 2**40 - 1000, 10**12 + 7, 10**15 - 200_001,
                                 11609864264058592345 // 1000, 2**50 + 3 * 2**17 + 5])
 def test_sieve_windows(mt, y1):
