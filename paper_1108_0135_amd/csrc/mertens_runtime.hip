@@ -182,7 +182,8 @@ struct Tuning {
 
 // Primes p in [5, limit] (limit <= 2^32) into pr, ascending: segmented
 // Eratosthenes over odd numbers, 2^19 of them per segment, crossed off by the
-// base primes up to sqrt(limit).
+// base primes up to sqrt(limit).  Large limits split the segments over up to
+// 16 host threads (contiguous runs, joined in order).
 void host_primes(uint64_t limit, std::vector<uint32_t> &pr)
 {
     pr.clear();
@@ -195,26 +196,51 @@ void host_primes(uint64_t limit, std::vector<uint32_t> &pr)
             for (uint64_t j = i * i; j <= root; j += 2 * i)
                 bc[j / 2] = 1;
         }
-    pr.reserve((size_t)(1.1 * (double)limit / std::max(1.0, std::log((double)limit))) + 16);
     constexpr uint64_t SPAN = 1ull << 19;  // odd numbers per segment
-    std::vector<uint8_t> comp(SPAN);
-    for (uint64_t lo = 1; lo <= limit; lo += 2 * SPAN) {  // odd v in [lo, lo + 2 SPAN)
-        std::fill(comp.begin(), comp.end(), 0);
-        const uint64_t hi = std::min(lo + 2 * SPAN - 1, limit);
-        for (uint32_t q : base) {
-            const uint64_t qq = (uint64_t)q * q;
-            if (qq > hi)
+    const uint64_t nseg = limit / (2 * SPAN) + 1;
+    const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    const uint64_t nthr = limit < (1ull << 26) ? 1 : std::min<uint64_t>(hw, nseg);
+    std::vector<std::vector<uint32_t>> part(nthr);
+    auto work = [&](uint64_t t) {
+        std::vector<uint8_t> comp(SPAN);
+        std::vector<uint32_t> &out = part[t];
+        const uint64_t s0 = nseg * t / nthr, s1 = nseg * (t + 1) / nthr;
+        for (uint64_t sg = s0; sg < s1; ++sg) {
+            const uint64_t lo = 1 + sg * 2 * SPAN;  // odd v in [lo, lo + 2 SPAN)
+            if (lo > limit)
                 break;
-            uint64_t f = std::max(qq, (lo + q - 1) / q * q);
-            if (f % 2 == 0)
-                f += q;
-            for (uint64_t v = f; v <= hi; v += 2 * q)
-                comp[(v - lo) / 2] = 1;
+            std::fill(comp.begin(), comp.end(), 0);
+            const uint64_t hi = std::min(lo + 2 * SPAN - 1, limit);
+            for (uint32_t q : base) {
+                const uint64_t qq = (uint64_t)q * q;
+                if (qq > hi)
+                    break;
+                uint64_t f = std::max(qq, (lo + q - 1) / q * q);
+                if (f % 2 == 0)
+                    f += q;
+                for (uint64_t v = f; v <= hi; v += 2 * q)
+                    comp[(v - lo) / 2] = 1;
+            }
+            for (uint64_t v = std::max<uint64_t>(lo, 5); v <= hi; v += 2)
+                if (!comp[(v - lo) / 2])
+                    out.push_back((uint32_t)v);
         }
-        for (uint64_t v = std::max<uint64_t>(lo, 5); v <= hi; v += 2)
-            if (!comp[(v - lo) / 2])
-                pr.push_back((uint32_t)v);
+    };
+    if (nthr == 1) {
+        work(0);
+    } else {
+        std::vector<std::thread> th;
+        for (uint64_t t = 0; t < nthr; ++t)
+            th.emplace_back(work, t);
+        for (std::thread &x : th)
+            x.join();
     }
+    size_t total = 0;
+    for (const auto &v : part)
+        total += v.size();
+    pr.reserve(total);
+    for (const auto &v : part)
+        pr.insert(pr.end(), v.begin(), v.end());
 }
 
 // ---------------------------------------------------------------------------
