@@ -6,8 +6,10 @@ pass of the hot path for n = 10^16 with u = 5*10^10 and y-blocks of 2^30
 per-block contribution update -> finalize.  The metric is sieved y per
 second through the update (the sweep covers y in [0, floor(n/(L+1))]);
 every step's result is checked against Table 1 of the paper.  The line also
-carries a small batched-vs-plain comparison, the roofline of the dominant
-kernel (HIP events on the library stream) and the CPU oracle's rate.
+carries the batched workload (256 n log-uniform in [1e13, 1e17] plus 1e16
+and 1e17) as one shared sweep against one query at a time, the roofline of
+the dominant kernel (HIP events on the library stream) and the CPU oracle
+timed on the host (one core, and one process per core).
 
 Other workloads (``--workload``), reported separately:
   batched  256 n log-uniform in [1e13, 1e17] (seed 0) plus 1e16 and 1e17,
@@ -47,6 +49,8 @@ INT_VALU_PEAK_TOPS = CU * LANES * CLOCK_GHZ / 1000.0  # 39.3 T int32 lane-ops/s
 # near-integer offset and test (add, compare), accumulate (add)
 OPS_PER_QUOTIENT = 6
 RECORD_BYTES = 16  # one sieve record: M(y) checkpoint and mu bits of 32 y
+# the method's own need per explicit-k pair: one int32 M(y) read at a random y
+GATHER_BYTES = 4
 
 
 def kernel_source_sha256() -> str:
@@ -71,25 +75,97 @@ def traffic_per_launch(kernel: str, workload: str = "n1e16"):
     return d["hbm_bytes_per_launch"]
 
 
-def cpu_baseline(budget_s: float = 15.0) -> dict:
-    """The oracle's exact block sieve (O1) over [1, N] on one host core."""
+def progress(msg: str) -> None:
+    """A progress line on stderr (long runs stay visibly alive)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+def host_cpu() -> dict:
+    """Host core count (usable by this process) and CPU model."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"nproc": usable, "cpu_count": os.cpu_count(), "model": model}
+
+
+def _o2_child(conn, T: int, n: int) -> None:
+    import oracle
+    o2 = oracle.IdentityOracle(T)
+    t0 = time.perf_counter()
+    m = o2.query(n)[0]
+    conn.send((m, time.perf_counter() - t0))
+    conn.close()
+
+
+def cpu_baseline(sieved_y: float, gpu_m_sample: int | None = None) -> dict:
+    """The oracle per query, on the host cores.
+
+    O2 (the Section 2 identity, recursively, on an O1 table M(0..T)) is
+    timed on one core for M(10^12) with T = 10^8: 10^12 = 10^16 / 10^4 is
+    the byproduct M(floor(n/c)) of the workload at c = 10^4, so this is a
+    bounded piece of the same query.  The time for M(10^16) itself is
+    extrapolated (labelled) from O2's cost, T for the table plus n / sqrt(T)
+    for the recursion, at the largest table that fits a host comfortably
+    (T = 2^31, 8 GiB).  `value` is the workload's sieved y (the GPU sweep's
+    work for one M(10^16)) over that extrapolated oracle time, so it reads in
+    the metric's unit.  The all-cores figure runs one O2 process per core on
+    the same 10^12 query (queries are independent).  The oracle's M(10^12)
+    must equal the GPU's byproduct at c = 10^4 (gpu_m_sample)."""
+    import multiprocessing as mp
     import oracle
     oracle.build()
-    lib = oracle.default()
-    N = 2 * 10**8
+    T_s, n_s, T_big = 10**8, 10**12, 2**31
     t0 = time.perf_counter()
-    lib.mertens_many([N])
-    dt = time.perf_counter() - t0
-    reps = 1
-    while dt * (reps + 1) / reps < budget_s and reps < 8:
-        t1 = time.perf_counter()
-        lib.mertens_many([N])
-        dt += time.perf_counter() - t1
-        reps += 1
-    return {"value": N * reps / dt, "unit": "sieved y/s", "cores": 1, "kind": "oracle",
-            "sample": f"O1 exact block sieve + running sum of y in [1, {N:.0e}] x{reps} "
-                      f"(single thread, {dt:.1f} s); the oracle has no update step, and its "
-                      f"M(1e16) would need the whole [1, 1e16] sieved"}
+    o2 = oracle.IdentityOracle(T_s)
+    t_table = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    m_s = o2.query(n_s)[0]
+    t_query = time.perf_counter() - t0
+    if gpu_m_sample is not None and m_s != gpu_m_sample:
+        raise RuntimeError(f"oracle M(1e12) = {m_s} differs from the GPU byproduct {gpu_m_sample}")
+    # extrapolation: table linear in T; recursion proportional to n / sqrt(T)
+    t_ext = t_table * T_big / T_s + t_query * (N_WORK / n_s) * (T_s / T_big) ** 0.5
+    cpu = host_cpu()
+    procs = max(1, min(cpu["nproc"], 16))
+    ctx = mp.get_context("spawn")
+    pipes, kids = [], []
+    t0 = time.perf_counter()
+    for _ in range(procs):
+        a, b = ctx.Pipe(duplex=False)
+        pr = ctx.Process(target=_o2_child, args=(b, T_s, n_s))
+        pr.start()
+        pipes.append(a)
+        kids.append(pr)
+    res = [a.recv() for a in pipes]
+    for pr in kids:
+        pr.join()
+    t_all = time.perf_counter() - t0
+    if any(m != m_s for m, _ in res):
+        raise RuntimeError("oracle processes disagree")
+    return {"value": sieved_y / t_ext, "unit": "sieved y/s",
+            "cores": 1, "kind": "oracle",
+            "sample": (f"O2 single thread for M(1e12) = M(1e16 // 1e4), the workload's byproduct "
+                       f"at c = 1e4: table T = 1e8 in {t_table:.2f} s + recursion {t_query:.2f} s; "
+                       f"M(1e16) EXTRAPOLATED to {t_ext:.0f} s at T = 2^31 (table linear in T, "
+                       f"recursion in n / sqrt(T)); value = the GPU sweep's {sieved_y:.3g} y "
+                       f"for one M(1e16) over that time"),
+            "per_query_s": {"n=1e12 measured (T=1e8, incl. table)": t_table + t_query,
+                            "n=1e16 extrapolated (T=2^31)": t_ext},
+            "all_cores": {"processes": procs, "wall_s": t_all,
+                          "queries_per_s": procs / t_all,
+                          "sample": f"{procs} independent O2 processes, each M(1e12) with its "
+                                    f"own T = 1e8 table"},
+            "host": cpu}
 
 
 def batched_vs_plain(mt, ns) -> dict:
@@ -97,7 +173,11 @@ def batched_vs_plain(mt, ns) -> dict:
     mt.init(0, 0)
     mt.query(ns[:2])  # warm
     t0 = time.perf_counter()
-    plain = [int(mt.query([n])[0]) for n in ns]
+    plain = []
+    for i, n in enumerate(ns):
+        plain.append(int(mt.query([n])[0]))
+        if i % 64 == 63:
+            progress(f"one at a time: {i + 1} of {len(ns)}")
     t_plain = time.perf_counter() - t0
     t0 = time.perf_counter()
     batched = [int(v) for v in mt.query(ns)]
@@ -107,12 +187,14 @@ def batched_vs_plain(mt, ns) -> dict:
     st = mt.stats()
     return {"queries": len(ns), "plain_qps": len(ns) / t_plain, "batched_qps": len(ns) / t_batch,
             "speedup": t_plain / t_batch, "plain_s": t_plain, "batched_s": t_batch,
-            "batched_u": st["u"], "batched_sieved_y": st["sieved_y"]}
+            "batched_u": st["u"], "batched_sieved_y": st["sieved_y"],
+            "batched_blocks": st["blocks"], "results": batched}
 
 
 def workload_default(args, mt) -> dict:
     import torch
 
+    progress("default workload: M(1e16)")
     mt.init(U_WORK, BLOCK_WORK)
     ahead = 1 if args.in_turn else 4
     mt.set_param("sieve_ahead", ahead)
@@ -150,11 +232,15 @@ def workload_default(args, mt) -> dict:
     sieve_ms_launch = seq["ms_sieve"] / seq["sieve_launches"]
     quot = seq["rl_quotients"] + seq["k_quotients"]
     upd_tops = quot / launches * OPS_PER_QUOTIENT / (upd_ms_launch * 1e-3) / 1e12
-    # update: algorithmic HBM bytes = one 16-byte record per explicit-k pair
-    # (a random M(y) read) + the run-length masks (8 bytes per 32 y) read once
-    # per 64-x tile over y <= Y
-    upd_bytes = (RECORD_BYTES * seq["k_quotients"] + 0.25 * seq["sum_Y"] / 64) / launches
+    # update: the method's HBM bytes = one int32 M(y) per explicit-k pair (a
+    # random read) + the run-length masks (8 bytes per 32 y) read once per
+    # 64-x tile over y <= Y; the record-layout view counts the 16-byte record
+    # this build reads per explicit-k pair instead
+    mask_bytes = 0.25 * seq["sum_Y"] / 64
+    upd_bytes = (GATHER_BYTES * seq["k_quotients"] + mask_bytes) / launches
     upd_gbs = upd_bytes / (upd_ms_launch * 1e-3) / 1e9
+    rec_bytes = (RECORD_BYTES * seq["k_quotients"] + mask_bytes) / launches
+    rec_gbs = rec_bytes / (upd_ms_launch * 1e-3) / 1e9
     # sieve: the records it writes, 0.5 byte per y
     sieve_gbs = (sieved / seq["sieve_launches"]) * 0.5 / (sieve_ms_launch * 1e-3) / 1e9
     if seq["ms_update"] >= seq["ms_sieve"]:
@@ -162,8 +248,13 @@ def workload_default(args, mt) -> dict:
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": upd_gbs / HBM_PEAK_GBS,
                 "traffic": traffic_per_launch("k_update"),
                 "algorithmic_bytes_per_launch": upd_bytes,
+                "bytes_rule": (f"{GATHER_BYTES} B (one int32 M(y)) per explicit-k pair + 8 B "
+                               f"of mu masks per 32 y per 64-x tile of the run-length part"),
                 "avg_launch_ms": upd_ms_launch, "launches": launches,
                 "quotients_per_launch": quot / launches,
+                "record_layout_view": {"achieved": rec_gbs, "frac": rec_gbs / HBM_PEAK_GBS,
+                                       "bytes_per_launch": rec_bytes,
+                                       "rule": f"{RECORD_BYTES} B record per explicit-k pair"},
                 "alu_view": {"achieved_Tops": upd_tops, "peak_Tops": INT_VALU_PEAK_TOPS,
                              "frac": upd_tops / INT_VALU_PEAK_TOPS,
                              "ops_per_quotient": OPS_PER_QUOTIENT}}
@@ -198,28 +289,37 @@ def workload_default(args, mt) -> dict:
         "quotients": {"run_length": st["rl_quotients"], "explicit_k": st["k_quotients"]},
         "roofline": roof,
     }
+    # the byproduct M(10^16 // 10^4) = M(10^12), checked against the oracle
+    line["byproduct_1e12"] = int(mt.byproducts(0, 10**4)[10**4 - 1])
+    line["tuning"] = mt.tuning()
     if not args.no_batched:
-        from paper_1108_0135_amd import inputs
-        ns = [int(v) for v in inputs.batch_log_uniform(seed=0, count=16, lo=1e13, hi=1e15)]
-        line["batched_sample"] = dict(batched_vs_plain(mt, ns),
-                                      workload="16 n log-uniform in [1e13, 1e15], seed 0")
+        progress("batched workload: 258 n, one at a time and as one sweep")
+        line["batched"] = dict(batched_workload(mt), workload=BATCHED_WORKLOAD)
     return line
 
 
-def workload_batched(args, mt) -> dict:
+BATCHED_WORKLOAD = ("256 n log-uniform in [1e13, 1e17] (seed 0) + 1e16 + 1e17: one shared "
+                    "sweep (automatic u) vs each n alone")
+
+
+def batched_workload(mt) -> dict:
+    """The batched workload as one shared sweep against one query at a time;
+    Table 1 pins two members."""
     from paper_1108_0135_amd import inputs
     ns = [int(v) for v in inputs.batch_log_uniform(seed=0, count=256, lo=1e13, hi=1e17)]
     ns += [10**16, 10**17]
     res = batched_vs_plain(mt, ns)
-    mt.init(0, 0)
-    out = mt.query(ns)
-    if int(out[-2]) != inputs.TABLE1[10**16] or int(out[-1]) != inputs.TABLE1[10**17]:
+    if res["results"][-2] != inputs.TABLE1[10**16] or res["results"][-1] != inputs.TABLE1[10**17]:
         raise RuntimeError("batched Table 1 values wrong")
+    del res["results"]
+    return res
+
+
+def workload_batched(args, mt) -> dict:
+    res = batched_workload(mt)
     return {"metric": METRIC, "value": res["batched_qps"], "unit": "queries/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "u64", "data": "synthetic",
-            "config": {"workload": "256 n log-uniform in [1e13,1e17] (seed 0) + 1e16 + 1e17, "
-                                   "one shared sweep vs one at a time"},
-            **res}
+            "config": {"workload": BATCHED_WORKLOAD}, "tuning": mt.tuning(), **res}
 
 
 def workload_serving(args, mt) -> dict:
@@ -438,7 +538,9 @@ def main() -> int:
         if args.workload == "default":
             line = workload_default(args, mt)
             if not args.no_cpu_baseline:
-                line["cpu_baseline"] = cpu_baseline()
+                progress("oracle timing on the host")
+                line["cpu_baseline"] = cpu_baseline(line["config"]["sieved_y"],
+                                                    line["byproduct_1e12"])
         elif args.workload == "batched":
             line = workload_batched(args, mt)
         elif args.workload == "interval":

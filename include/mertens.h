@@ -194,6 +194,13 @@ int mertens_set_stream(void *hip_stream);
 int mertens_set_param(const char *key, double value);
 
 /*
+ * mertens_get_param -- the current value of a mertens_set_param key (the
+ * defaults until changed; mertens_init restores them) into *value.
+ * Returns 0, or MERTENS_EINVAL for an unknown key or a NULL pointer.
+ */
+int mertens_get_param(const char *key, double *value);
+
+/*
  * mertens_stats -- counters of the last mertens_query or mertens_interval (benchmarking).
  * Writes up to cap doubles into vals in this order (returns how many):
  *   0 sieved y (Ymax+1)   1 blocks         2 u used        3 sum of L

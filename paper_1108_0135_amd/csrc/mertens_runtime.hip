@@ -831,6 +831,7 @@ struct ServeQuery {
     double t_submit = 0, latency = 0;
     int64_t result = 0;
     int state = 0;  // 0 queued, 1 in the sweep, 2 done, 3 failed
+    int error = 0;  // state 3: the code its mertens_poll returns
     uint32_t idx = 0;
     uint64_t last_block = 0, seen = 0;
     std::vector<uint8_t> seen_map;
@@ -1061,10 +1062,18 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
         if (!rc)
             rc = bt.update_block(bm, grid, s, nullptr);
         const hipError_t ec = hipStreamEndCapture(s, &graph);
-        if (rc)
-            return rc;
-        HIPCHK(ec);
-        HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        if (rc || ec != hipSuccess) {
+            if (graph)
+                (void)hipGraphDestroy(graph);
+            if (rc)
+                return rc;
+            HIPCHK(ec);
+        }
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            HIPCHK(ei);
+        }
         hipError_t el = hipSuccess;
         for (uint64_t bi = 0; bi < nblocks && el == hipSuccess; ++bi)
             el = hipGraphLaunch(exec, s);
@@ -1327,9 +1336,24 @@ int serve_step(std::vector<uint64_t> &admit)
             const uint64_t L = std::max<uint64_t>(1, n / u);
             by_lane[(n / (L + 1)) / B < g.serve_short_blocks ? 0 : 1].push_back(t);
         }
-        for (auto &tl : by_lane)
-            if (!tl.empty())
-                RCCHK(serve_admit(tl, B));
+        for (auto &tl : by_lane) {
+            if (tl.empty())
+                continue;
+            const int rc = serve_admit(tl, B);
+            if (rc != 0) {
+                // only this batch fails: its tickets report rc, their x
+                // entries return to the budget, and the sweep goes on
+                std::lock_guard<std::mutex> lk(v.mu);
+                for (uint64_t t : tl) {
+                    ServeQuery &q = v.queries[t];
+                    const uint64_t u = g.u_req ? g.u_req : auto_u((long double)q.n, g.tune.u_scale);
+                    const uint64_t need = std::max<uint64_t>(1, q.n / u);
+                    v.x_used -= std::min(v.x_used, need);
+                    q.state = 3;
+                    q.error = rc;
+                }
+            }
+        }
     }
     for (ServeLane &ln : v.lanes)
         RCCHK(serve_lane_step(ln, B));
@@ -1716,6 +1740,19 @@ int mertens_submit(uint64_t n, uint64_t *ticket)
         return MERTENS_EINVAL;
     if (!g.ready)
         return MERTENS_ENODEV;
+    // the request's own split must give a plan (as Batch::plan requires)
+    if (n > 0) {
+        const uint64_t u = g.u_req ? g.u_req : auto_u((long double)n, g.tune.u_scale);
+        const uint64_t Lw = n / u;
+        if (Lw >= (1ull << 31)) {
+            set_error_text("u too small for this n: its array would need 2^31 or more entries");
+            return MERTENS_EINVAL;
+        }
+        if ((n / ((Lw < 1 ? 1 : Lw) + 1)) >> 62) {
+            set_error_text("u too large for this n: the sieve bound n/(L+1) must stay below 2^62");
+            return MERTENS_EINVAL;
+        }
+    }
     Server &v = g.srv;
     if (!v.running)
         RCCHK(serve_start());
@@ -1753,8 +1790,9 @@ int mertens_poll(uint64_t ticket, int64_t *out, double *latency_s)
         return MERTENS_ERANGE;
     ServeQuery &q = it->second;
     if (q.state == 3) {
+        const int rc = q.error ? q.error : (v.failure ? v.failure : MERTENS_EIO);
         v.queries.erase(it);
-        return v.failure ? v.failure : MERTENS_EIO;
+        return rc;
     }
     if (q.state != 2)
         return MERTENS_EINPROGRESS;
@@ -1853,6 +1891,48 @@ int mertens_set_param(const char *key, double value)
     } else {
         return MERTENS_EINVAL;
     }
+    return 0;
+}
+
+int mertens_get_param(const char *key, double *value)
+{
+    if (!key || !value)
+        return MERTENS_EINVAL;
+    const Tuning &t = g.tune;
+    if (!strcmp(key, "u_scale"))
+        *value = t.u_scale;
+    else if (!strcmp(key, "graph"))
+        *value = t.graph ? 1.0 : 0.0;
+    else if (!strcmp(key, "progress"))
+        *value = (double)t.progress;
+    else if (!strcmp(key, "wide_bits"))
+        *value = t.wide_bits;
+    else if (!strcmp(key, "beta"))
+        *value = t.beta;
+    else if (!strcmp(key, "ychunk"))
+        *value = t.ychunk;
+    else if (!strcmp(key, "kchunk"))
+        *value = t.kchunk;
+    else if (!strcmp(key, "kbal"))
+        *value = t.kbal;
+    else if (!strcmp(key, "bucket_min"))
+        *value = g.ss.bucket_min;
+    else if (!strcmp(key, "rl_fast"))
+        *value = t.rl_fast;
+    else if (!strcmp(key, "update_window"))
+        *value = t.update_window;
+    else if (!strcmp(key, "sieve_ahead"))
+        *value = t.sieve_ahead;
+    else if (!strcmp(key, "waves_per_cu"))
+        *value = t.waves_per_cu;
+    else if (!strcmp(key, "serve_capacity"))
+        *value = (double)g.serve_capacity;
+    else if (!strcmp(key, "serve_short_blocks"))
+        *value = (double)g.serve_short_blocks;
+    else if (!strcmp(key, "serve_x_budget"))
+        *value = (double)g.serve_x_budget;
+    else
+        return MERTENS_EINVAL;
     return 0;
 }
 

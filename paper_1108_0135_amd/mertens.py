@@ -36,6 +36,7 @@ _sig = {
     "mertens_query_wide": ([_P(_u64), _P(_u64), _sz, _P(_i64)], ctypes.c_int),
     "mertens_set_stream": ([ctypes.c_void_p], ctypes.c_int),
     "mertens_set_param": ([ctypes.c_char_p, ctypes.c_double], ctypes.c_int),
+    "mertens_get_param": ([ctypes.c_char_p, _P(ctypes.c_double)], ctypes.c_int),
     "mertens_stats": ([_P(ctypes.c_double), ctypes.c_int], ctypes.c_int),
     "mertens_shutdown": ([], None),
     "mertens_strerror": ([ctypes.c_int], ctypes.c_char_p),
@@ -163,6 +164,21 @@ def interval(a: int, b: int, m_a: int | None = None, values: bool = False) -> di
 
 def set_param(key: str, value: float) -> None:
     _check(_lib.mertens_set_param(key.encode(), float(value)), f"mertens_set_param({key})")
+
+
+TUNING_KEYS = ["u_scale", "beta", "ychunk", "kchunk", "kbal", "waves_per_cu", "graph",
+               "sieve_ahead", "update_window", "bucket_min", "rl_fast", "wide_bits"]
+
+
+def get_param(key: str) -> float:
+    v = ctypes.c_double(0.0)
+    _check(_lib.mertens_get_param(key.encode(), ctypes.byref(v)), f"mertens_get_param({key})")
+    return v.value
+
+
+def tuning() -> dict:
+    """The tuning parameters the library currently runs with."""
+    return {k: get_param(k) for k in TUNING_KEYS}
 
 
 def set_stream(stream_handle: int | None) -> None:

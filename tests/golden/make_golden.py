@@ -4,7 +4,8 @@ Calls only the CPU oracle (``oracle/``) on the seeded inputs of
 ``paper_1108_0135_amd.inputs``; never the GPU path.  Re-run after any change
 to the oracle's arithmetic:  python tests/golden/make_golden.py
 (``--only-intervals tests/golden/golden.json`` refreshes just the interval
-entries of an existing file.)
+entries of an existing file, ``--only-batch256 tests/golden/golden.json``
+just the batched-workload entries.)
 """
 from __future__ import annotations
 
@@ -47,6 +48,43 @@ def interval_cases(out: dict) -> None:
     out["extreme_window"] = {"a": a, "b": b, "m_a": m_a, **r, "samples": samples}
 
 
+BATCH256_MAX = 3 * 10**14  # the members of the batched workload O2 reaches in minutes
+BATCH256_BYP_C = 200        # byproducts c <= this of the largest such member
+
+
+def _o2_worker(n: int) -> int:
+    return _O2_SHARED.query(n)[0]
+
+
+_O2_SHARED = None
+
+
+def batch256_cases(out: dict, workers: int = 7, T: int = 4 * 10**9) -> None:
+    """The batched workload (256 n log-uniform in [1e13, 1e17], seed 0): O2 for
+    every member up to BATCH256_MAX, and sampled byproducts of the largest.
+
+    One O1 table M(0..T) is built once and shared by forked worker processes
+    (copy-on-write, read only); each O2 evaluation runs single-threaded."""
+    import multiprocessing as mp
+    global _O2_SHARED
+    ns = [int(v) for v in inputs.batch_log_uniform(seed=0, count=256, lo=1e13, hi=1e17)]
+    idx = [i for i, n in enumerate(ns) if n <= BATCH256_MAX]
+    _O2_SHARED = oracle.IdentityOracle(T)
+    order = sorted(idx, key=lambda i: -ns[i])  # largest first: better balance
+    with mp.get_context("fork").Pool(workers) as pool:
+        vals = pool.map(_o2_worker, [ns[i] for i in order], chunksize=1)
+    got = dict(zip(order, vals))
+    big = max(idx, key=lambda i: ns[i])
+    rng = np.random.default_rng(11)
+    cs = sorted({int(c) for c in rng.integers(2, BATCH256_BYP_C + 1, 12)} | {2, BATCH256_BYP_C})
+    m, byp = _O2_SHARED.query(ns[big], BATCH256_BYP_C)
+    assert m == got[big]
+    out["batch256"] = {"seed": 0, "max_n": BATCH256_MAX, "index": idx,
+                       "n": [ns[i] for i in idx], "M": [int(got[i]) for i in idx],
+                       "byproducts_of": big, "c": cs, "byproducts": [int(byp[c - 1]) for c in cs]}
+    _O2_SHARED = None
+
+
 def main() -> None:
     t0 = time.time()
     if len(sys.argv) > 2 and sys.argv[1] == "--only-intervals":
@@ -54,6 +92,14 @@ def main() -> None:
         path = sys.argv[2]
         out = json.load(open(path))
         interval_cases(out)
+        with open(path, "w") as f:
+            json.dump(out, f)
+        print(f"updated {path} in {time.time() - t0:.1f} s")
+        return
+    if len(sys.argv) > 2 and sys.argv[1] == "--only-batch256":
+        path = sys.argv[2]
+        out = json.load(open(path))
+        batch256_cases(out)
         with open(path, "w") as f:
             json.dump(out, f)
         print(f"updated {path} in {time.time() - t0:.1f} s")
@@ -95,6 +141,7 @@ def main() -> None:
     out["window1e19_diffs"] = {"seed": 0, "n": nd, "diffs": diffs}
 
     interval_cases(out)
+    batch256_cases(out)
 
     path = os.path.join(HERE, "golden.json")
     with open(path, "w") as f:

@@ -48,3 +48,14 @@ def test_interval1e12(o2):
     r = oracle.interval(a, b, m_a)
     assert r == {k: g[k] for k in ("m_b", "n_min", "m_min", "n_max", "m_max")}
     assert o2.query(b)[0] == g["m_b"]
+
+
+def test_batch256_smallest_member():
+    # the batched workload's goldens: the inputs from their seed, and the
+    # smallest member's M(n) recomputed by O2 (about 15 s)
+    g = GOLDEN["batch256"]
+    ns = [int(v) for v in inputs.batch_log_uniform(seed=g["seed"], count=256, lo=1e13, hi=1e17)]
+    assert [ns[i] for i in g["index"]] == g["n"]
+    assert g["index"] == [i for i, n in enumerate(ns) if n <= g["max_n"]]
+    k = min(range(len(g["n"])), key=lambda i: g["n"][i])
+    assert oracle.IdentityOracle(3 * 10**8).query(g["n"][k])[0] == g["M"][k]

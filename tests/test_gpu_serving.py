@@ -92,3 +92,21 @@ def test_short_request_overtakes_long_sweep(mt):
     assert got[short_t][0] == GOLDEN["seeded32"]["M"][0]
     assert mt.poll(long_t) is None  # still sweeping
     assert _collect(mt, [long_t], timeout=300)[long_t][0] == inputs.TABLE1[10**17]
+
+
+def test_bad_request_beside_good_ones(mt):
+    # with an explicit small u, an n whose array would need 2^31 or more
+    # entries is refused at submission; the requests around it complete
+    # exactly and the worker keeps serving
+    from paper_1108_0135_amd import mertens as binding
+    mt.init(1000, 1 << 20)
+    good = GOLDEN["seeded32"]["n"][:6]
+    tickets = [mt.submit(n) for n in good[:3]]
+    with pytest.raises(binding.MertensError) as err:
+        mt.submit(10**13)  # L = 10^10 >= 2^31
+    assert err.value.code == binding.EINVAL
+    tickets += [mt.submit(n) for n in good[3:]]
+    got = _collect(mt, tickets)
+    assert [got[t][0] for t in tickets] == GOLDEN["seeded32"]["M"][:6]
+    t = mt.submit(GOLDEN["batch48"]["n"][0])
+    assert _collect(mt, [t])[t][0] == GOLDEN["batch48"]["M"][0]
