@@ -13,10 +13,14 @@ constexpr uint32_t SEG = 1u << 17;
 constexpr uint32_t SEG_WORDS = SEG / 64;     // 64-y mask words per segment
 constexpr int SIEVE_THREADS = 1024;          // 16 waves, 2 mask words per thread
 // Pre-sieved pattern: log sums of 2,3,5,7,11,13 and square flags of 4 and 9
-// repeat with period lcm(2,3,5,7,11,13,4,9) = 180180.  Four copies shifted
-// by 0, 4, 8, 12 bytes let every segment copy it with 16-byte loads.
+// repeat with period lcm(2,3,5,7,11,13,4,9) = 180180.  It is stored in the
+// sieve's LDS layout (32-y groups, y offset t of a group in word t & 7,
+// byte t >> 3) in eight copies that start 0, 4, ..., 28 pattern bytes late,
+// so every segment (which starts at a multiple of 4 in the pattern) is one
+// run of whole 32-byte groups of one copy.
 constexpr uint32_t PAT = 180180;
-constexpr uint32_t PAT_WORDS = ((PAT + SEG) / 4 + 16 + 3) & ~3u;  // uint32 per copy
+constexpr uint32_t PAT_COPIES = 8;
+constexpr uint32_t PAT_WORDS = ((PAT + SEG + 31) / 32) * 8;  // uint32 per copy
 // Sieving primes below this bound (>= 64 multiples per segment) are walked by
 // a whole wavefront, lane i taking the i-th multiple; larger ones by one lane.
 constexpr uint32_t SMALL_P = SEG / 64;

@@ -701,225 +701,421 @@ __device__ inline int64_t seg_lookback(const uint64_t *st, uint32_t seg)
     }
 }
 
-// One workgroup per segment of SEG consecutive y.  LDS holds one byte per y:
-// bits 0-6 accumulate l_p = ceil(log2 p)|1 over sieving primes p | y, bit 7
-// flags a square divisor.  Four y share a 32-bit LDS word; sums stay below
-// 128 so bytes never carry into each other, and atomics make the prime
-// walks order-free.  Classification (corrected log rule, y >= 4):
-//   bit 7 set                        -> mu = 0
-//   A >= floor(log2 y) (fully split) -> mu = (-1)^A
-//   otherwise (one prime > Psieve)   -> mu = -(-1)^A
-// (A's parity is the number of sieving primes dividing y, as every l_p is
-// odd.)  Segments are claimed in ticket order; each writes whole 16-byte
-// records per 32 y (mu = +1 and -1 bits, M(y) before the record), the M(y)
-// prefix coming from a workgroup scan plus a look-back over earlier
-// segments.
+// The sieve of Section 3 with the corrected log rule.  LDS holds one byte
+// per y of a segment of SEG consecutive y: bits 0-6 accumulate
+// l_p = ceil(log2 p)|1 over the sieving primes p | y on top of a bias of
+// 64 - floor(log2 y), bit 7 flags a square divisor.  With A the log sum and
+// T = floor(log2 y), the byte holds A + 64 - T < 128 (A < T + 1 + 2 omega(y)),
+// so bytes never carry into each other and:
+//   bit 7 set                           -> mu = 0
+//   bit 6 set (A >= T, fully split)     -> mu = (-1)^A
+//   otherwise (one prime above Psieve)  -> mu = -(-1)^A
+// where A's parity (every l_p is odd) is bit 0 flipped when T is odd.
+//
+// Layout: 32-y group G (one record) holds y offsets 32G + t in eight
+// 32-bit words, offset t in word t & 7, byte t >> 3.  The bits 7, 6 and 0
+// of the eight words then gather into the group's 32-bit masks in y order
+// by shifts alone.  A prime walk with step 64p keeps both the byte and the
+// word within its group, so it advances by a constant 64p bytes.
+//
+// Each workgroup sieves SV_R consecutive segments (a group of segments
+// claimed in ticket order) and carries the per-prime offsets from one
+// segment to the next: the small primes' (one wavefront per prime) in
+// lane-distributed registers, the first SV_U * SIEVE_THREADS larger primes'
+// (one lane per prime) in per-thread registers.  The classified masks of
+// all SV_R segments stay in registers until the group's M(y) prefix is
+// known (workgroup scan plus decoupled look-back over earlier groups);
+// then whole 16-byte records are written.
+constexpr int SV_R = 4;
+constexpr int SV_U = 16;
+constexpr uint32_t SV_GROUPS = SEG / 32;                  // records per segment
+constexpr int SV_GPT = (int)(SV_GROUPS / SIEVE_THREADS);  // records per thread and segment
+static_assert(SV_GPT == 4, "four 16-bit count fields per thread and segment");
+
+// Byte address (in the segment's LDS) of the word holding y offset o, and
+// the shift of o's byte within it.
+__device__ inline uint32_t sv_addr(uint32_t o)
+{
+    return (o & ~31u) | ((o & 7u) << 2);
+}
+__device__ inline uint32_t sv_shift(uint32_t o)
+{
+    return o & 24u;
+}
+__device__ inline void sv_add(uint8_t *lb, uint32_t o, uint32_t v)
+{
+    atomicAdd(reinterpret_cast<uint32_t *>(lb + sv_addr(o)), v << sv_shift(o));
+}
+__device__ inline void sv_square(uint8_t *lb, uint32_t o)
+{
+    atomicOr(reinterpret_cast<uint32_t *>(lb + sv_addr(o)), 0x80u << sv_shift(o));
+}
+
+// mu masks of one 32-y group from its eight LDS words: pos (mu = +1) and
+// neg (mu = -1), bit t for y offset t; tpar = ~0 when T is odd.
+__device__ inline void sv_classify(const uint4 lo, const uint4 hi, uint32_t tpar, uint32_t &pos,
+                                   uint32_t &neg)
+{
+    const uint32_t w[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    uint32_t sq = 0, fu = 0, pa = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t m = 0x01010101u << k;
+        sq |= (w[k] >> (7 - k)) & m;
+        fu |= (k < 7 ? (w[k] >> (6 - k)) : (w[k] << 1)) & m;
+        pa |= (w[k] << k) & m;
+    }
+    const uint32_t nz = ~sq;
+    neg = nz & ~(fu ^ pa ^ tpar);
+    pos = nz & ~neg;
+}
+
+// The record of y in [0, 32): mu by trial division (y = 0 is a multiple of
+// every sieving prime, so its byte overflows and carries into the bytes of
+// y = 8, 16, 24 of the same word; mu(0) = 0 by convention).  Below 32 the
+// part left after removing 2, 3 and 5 is 1 or a prime.
+__device__ inline void sv_classify_first(uint32_t &pos, uint32_t &neg)
+{
+    pos = 0;
+    neg = 0;
+    for (uint32_t t = 1; t < 32; ++t) {
+        uint32_t v = t;
+        int m = 1;
+        for (uint32_t d = 2; d <= 5 && m != 0; d += (d == 2 ? 1u : 2u)) {
+            if (v % d == 0) {
+                v /= d;
+                m = (v % d == 0) ? 0 : -m;
+            }
+        }
+        if (m != 0 && v > 1)
+            m = -m;
+        if (m > 0)
+            pos |= 1u << t;
+        else if (m < 0)
+            neg |= 1u << t;
+    }
+}
+
+// Inclusive prefix over the wave of four 16-bit fields packed in a uint64.
+__device__ inline uint64_t wave_scan_u64(uint64_t x)
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const uint64_t t = __shfl_up(x, o, 64);
+        if (lane >= (uint32_t)o)
+            x += t;
+    }
+    return x;
+}
+
 __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
 {
     const BlockArgs b = load_block(b_in);
-    __shared__ uint32_t lds[SEG / 4];
-    __shared__ int64_t wsum[SIEVE_THREADS / 64];
-    __shared__ int64_t bcast[2];  // ticket, M(y) before the segment
+    constexpr uint32_t NWAVES = SIEVE_THREADS / 64;
+    __shared__ uint4 lds4[SEG / 16];
+    // per (segment, record slot) and wave: wave totals, then their exclusive prefix
+    __shared__ int32_t stot[SV_R * SV_GPT * NWAVES];
+    __shared__ int64_t bcast[2];  // ticket, M(y) before the group
+    uint8_t *lb = reinterpret_cast<uint8_t *>(lds4);
     const uint32_t tid = threadIdx.x, lane = lane_id();
     if (tid == 0)
         bcast[0] = atomicAdd(b.seg_ticket, 1u);
     __syncthreads();
-    const uint32_t seg = __builtin_amdgcn_readfirstlane((uint32_t)bcast[0]);
-    if (seg >= b.nseg)
+    const uint32_t grp = __builtin_amdgcn_readfirstlane((uint32_t)bcast[0]);
+    const uint32_t ngroups = (b.nseg + SV_R - 1) / SV_R;
+    if (grp >= ngroups)
         return;
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    constexpr uint32_t NWAVES = SIEVE_THREADS / 64;
-    const uint32_t segbase = seg * SEG;  // < 2^31
-    const uint64_t s0 = b.y1 + segbase;
+    const uint32_t seg0 = grp * SV_R;
+    const uint32_t nsegs = b.nseg - seg0 < (uint32_t)SV_R ? b.nseg - seg0 : (uint32_t)SV_R;
+    const uint32_t segbase0 = seg0 * SEG;  // < 2^31
 
-    // pre-sieved pattern (2,3,5,7,11,13 and squares 4, 9)
-    uint32_t po = b.pat_off + segbase % PAT;
-    if (po >= PAT)
-        po -= PAT;
-    // po is a multiple of 4: copy (po / 4) mod 4 starts 4 (po / 4 mod 4) bytes
-    // later, so the segment's bytes start 16-byte aligned in it
-    const uint4 *src = reinterpret_cast<const uint4 *>(
-        b.pat32 + (size_t)((po >> 2) & 3u) * PAT_WORDS + ((po >> 2) & ~3u));
-    uint4 *l4w = reinterpret_cast<uint4 *>(lds);
-    for (uint32_t j = tid; j < SEG / 16; j += SIEVE_THREADS)
-        l4w[j] = src[j];
-    __syncthreads();
-
-    // squares p^2 <= SQ_LDS_P^2: one wave per prime, lane i takes multiple i
-    for (uint32_t i = wave; i < b.n_sq_lds; i += NWAVES) {
-        const uint32_t p = b.pres[i].x;
-        const uint32_t p2 = p * p;  // < 2^21
-        uint32_t r = (uint32_t)b.res2[i] + segbase % p2;
-        if (r >= p2)
-            r -= p2;
-        const uint32_t first = r ? p2 - r : 0;
-        for (uint32_t o = first + lane * p2; o < SEG; o += 64 * p2)
-            atomicOr(&lds[o >> 2], 0x80u << ((o & 3u) << 3));
-    }
-    // small primes: one wave per prime, lane i takes multiples i, i+64, ...
-    for (uint32_t i = FIRST_SIEVED + wave; i < b.n_small; i += NWAVES) {
-        const uint2 e = b.pres[i];
-        const uint32_t p = e.x, lp = log_prime(p);
-        uint32_t r = e.y + segbase % p;  // both < p < SMALL_P
-        if (r >= p)
-            r -= p;
-        const uint32_t first = r ? p - r : 0;
-        for (uint32_t o = first + lane * p; o < SEG; o += 64 * p)
-            atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
-    }
-    // larger primes (at most SEG/SMALL_P = 64 multiples): one lane per prime,
-    // four primes' table entries loaded ahead of their walks
-    const uint32_t i0 = (b.n_small > FIRST_SIEVED ? b.n_small : FIRST_SIEVED) + tid;
-    const uint32_t i_end = b.n_bucket < b.n_sieve ? b.n_bucket : b.n_sieve;
-    for (uint32_t i = i0; i < i_end; i += 4 * SIEVE_THREADS) {
-        uint2 e[4];
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t k = i + (uint32_t)u * SIEVE_THREADS;
-            e[u] = k < i_end ? b.pres[k] : make_uint2(0u, 0u);
+    // ---- carried offsets (first multiple in the current segment)
+    // squares p^2, p <= SQ_LDS_P (index < n_sq_lds): wave w, lane j holds index w + 16 j
+    uint32_t q_p2 = 0, q_first = 0, q_step = 0;
+    {
+        const uint32_t i = wave + NWAVES * lane;
+        if (i < b.n_sq_lds) {
+            const uint32_t p = b.pres[i].x;
+            q_p2 = p * p;  // < 2^21
+            uint32_t r = (uint32_t)b.res2[i] + segbase0 % q_p2;
+            if (r >= q_p2)
+                r -= q_p2;
+            q_first = r ? q_p2 - r : 0;
+            q_step = SEG % q_p2;
         }
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const uint32_t p = e[u].x;
-            if (p == 0)
-                continue;
-            const uint32_t lp = log_prime(p);
-            uint64_t r = (uint64_t)e[u].y + segbase % p;
+    }
+    // small primes (index in [FIRST_SIEVED, n_small)): wave w, lane j holds
+    // index FIRST_SIEVED + w + 16 j
+    uint32_t s_p = 0, s_first = 0, s_step = 0;
+    {
+        const uint32_t i = FIRST_SIEVED + wave + NWAVES * lane;
+        if (i < b.n_small) {
+            const uint32_t p = b.pres[i].x;
+            s_p = p;
+            uint32_t r = b.pres[i].y + segbase0 % p;  // both < p < SMALL_P
             if (r >= p)
                 r -= p;
-            const uint64_t first = r ? p - r : 0;
-            for (uint64_t o = first; o < SEG; o += p)
-                atomicAdd(&lds[o >> 2], lp << ((o & 3u) << 3));
+            s_first = r ? p - r : 0;
+            s_step = SEG % p;
         }
     }
-    // bucketed primes (> SEG): their hits in this segment, listed per block
-    if (b.n_bucket < b.n_sieve) {
-        const uint32_t e1 = b.bk_start[seg + 1];
-        for (uint32_t k = b.bk_start[seg] + tid; k < e1; k += SIEVE_THREADS) {
-            const uint32_t v = b.bk_buf[k];
-            const uint32_t o = v & (SEG - 1);
-            atomicAdd(&lds[o >> 2], (v >> 17) << ((o & 3u) << 3));
+    const uint32_t nq_w = b.n_sq_lds > wave ? (b.n_sq_lds - wave + NWAVES - 1) / NWAVES : 0u;
+    const uint32_t ns_w =
+        b.n_small > FIRST_SIEVED + wave ? (b.n_small - FIRST_SIEVED - wave + NWAVES - 1) / NWAVES : 0u;
+    // larger primes, one lane each: the first SV_U per thread carried
+    // ({p | l_p << 24} and the next offset, which may pass SEG for p > SEG;
+    // absent ones keep an offset that never comes below SEG in SV_R steps).
+    // The carried primes are the 2^14 primes from SMALL_P on, all < 2^18.
+    const uint32_t lp0 = b.n_small > FIRST_SIEVED ? b.n_small : FIRST_SIEVED;
+    const uint32_t i_end = b.n_bucket < b.n_sieve ? b.n_bucket : b.n_sieve;
+    const uint32_t i_carry =
+        i_end - lp0 < (uint32_t)(SV_U * SIEVE_THREADS) ? i_end : lp0 + SV_U * SIEVE_THREADS;
+    uint32_t c_pl[SV_U], c_o[SV_U];
+#pragma unroll
+    for (int u = 0; u < SV_U; ++u) {
+        const uint32_t i = lp0 + tid + (uint32_t)u * SIEVE_THREADS;
+        c_pl[u] = 0;
+        c_o[u] = ~0u;
+        if (i < i_carry) {
+            const uint2 e = b.pres[i];  // p < 2^18 here (at most 2^14 primes past SMALL_P)
+            uint32_t r = e.y + segbase0 % e.x;
+            if (r >= e.x)
+                r -= e.x;
+            c_pl[u] = e.x | (log_prime(e.x) << 24);
+            c_o[u] = r ? e.x - r : 0;
         }
     }
-    // squares p^2 > SQ_LDS_P^2 (> SEG): at most one multiple each in the
-    // segment, listed in its bucket.  Should the bucket have overflowed,
-    // every such prime is checked here instead: f = offset of the block's
-    // first multiple; the segment's first is f - segbase mod p^2, with the
-    // quotient estimated in fp32 (t < 2^31, error < 1) and corrected once.
-    const uint32_t nsq = b.sq_cnt[seg];
-    if (nsq <= SQ_BUCKET) {
-        for (uint32_t k = tid; k < nsq; k += SIEVE_THREADS) {
-            const uint32_t o = b.sq_buf[(uint64_t)seg * SQ_BUCKET + k];
-            atomicOr(&lds[o >> 2], 0x80u << ((o & 3u) << 3));
-        }
-    }
-    for (uint32_t i = b.n_sq_lds + tid; nsq > SQ_BUCKET && i < b.n_sq; i += SIEVE_THREADS) {
-        const uint64_t p = b.pres[i].x;
-        const uint64_t d = p * p;
-        const uint64_t r2 = b.res2[i];
-        const uint64_t f = r2 ? d - r2 : 0;
-        uint64_t o;
-        if (f >= segbase) {
-            o = f - segbase;
-        } else {
-            const uint32_t t = segbase - (uint32_t)f;
-            const uint64_t qt = (uint64_t)((float)t / (float)d);
-            int64_t rem = (int64_t)t - (int64_t)(qt * d);
-            if (rem < 0)
-                rem += (int64_t)d;
-            else if (rem >= (int64_t)d)
-                rem -= (int64_t)d;
-            o = rem ? d - (uint64_t)rem : 0;
-        }
-        if (o < SEG)
-            atomicOr(&lds[o >> 2], 0x80u << ((uint32_t)(o & 3u) << 3));
-    }
-    __syncthreads();
 
-    // classify: thread t owns words t and t + SIEVE_THREADS of the segment
-    uint64_t nzw[2], ngw[2];
-    int64_t cnt[2];
+    uint32_t mpos[SV_R][SV_GPT], mneg[SV_R][SV_GPT];
+    uint64_t wex[SV_R];  // in-wave exclusive prefix of the four records' mu sums (16-bit fields)
+
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const uint32_t w = tid + (uint32_t)h * SIEVE_THREADS;
-        const uint64_t ybase = s0 + (uint64_t)w * 64;
-        const uint4 *l4 = reinterpret_cast<const uint4 *>(lds) + w * 4;
-        // floor(log2 y) is the same for the 64 y of a word (a power of two
-        // >= 64 only ever starts a word); only the block's first word, y < 64,
-        // takes it per group of 4 (y < 4 is patched below)
-        const uint32_t Tw = 63u - (uint32_t)__clzll((long long)(ybase | 1));
-        const bool low = ybase < 64;
-        uint64_t nz = 0, ng = 0;
+    for (int j = 0; j < SV_R; ++j) {
+        if ((uint32_t)j >= nsegs) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint4 v = l4[j];
-            const uint32_t vs[4] = {v.x, v.y, v.z, v.w};
+            for (int h = 0; h < SV_GPT; ++h) {
+                mpos[j][h] = mneg[j][h] = 0;
+                if (lane == 63)
+                    stot[(j * SV_GPT + h) * NWAVES + wave] = 0;
+            }
+            wex[j] = 0;
+            continue;
+        }
+        const uint32_t seg = seg0 + (uint32_t)j;
+        const uint32_t segbase = seg * SEG;
+        const uint64_t s0 = b.y1 + segbase;
+        // T = floor(log2 y) is one value on a segment from 2^17 on; below
+        // (the very first segment) it is taken per record
+        const bool first_seg = s0 < SEG;
+        const uint32_t Ts = 63u - (uint32_t)__clzll((long long)(s0 | 1));
+
+        // pre-sieved pattern (2,3,5,7,11,13 and squares 4, 9) plus the bias
+        uint32_t po = b.pat_off + segbase % PAT;
+        if (po >= PAT)
+            po -= PAT;
+        // copy (po / 4) mod 8 starts 4 ((po / 4) mod 8) pattern bytes later, so
+        // the segment is a whole run of 32-byte groups of it
+        const uint4 *src = reinterpret_cast<const uint4 *>(
+            b.pat32 + (size_t)((po >> 2) & 7u) * PAT_WORDS + (size_t)(po >> 5) * 8);
+        for (uint32_t q = tid; q < SEG / 16; q += SIEVE_THREADS) {
+            uint4 v = src[q];
+            uint32_t T = Ts;
+            if (first_seg) {
+                const uint32_t yg = (uint32_t)s0 + (q >> 1) * 32;
+                T = yg ? 31u - (uint32_t)__clz((int)yg) : 4u;
+            }
+            const uint32_t bias = (64u - T) * 0x01010101u;
+            v.x += bias;
+            v.y += bias;
+            v.z += bias;
+            v.w += bias;
+            lds4[q] = v;
+        }
+        __syncthreads();
+
+        // squares p^2 <= SQ_LDS_P^2: one wave per prime, lane i takes multiple i
+        for (uint32_t jj = 0; jj < nq_w; ++jj) {
+            const uint32_t p2 = __builtin_amdgcn_readlane(q_p2, jj);
+            const uint32_t f = __builtin_amdgcn_readlane(q_first, jj);
+            const uint32_t o = f + lane * p2;
+            if (o < SEG) {
+                const uint32_t v = 0x80u << sv_shift(o);
+                for (uint32_t a = sv_addr(o); a < SEG; a += 64 * p2)
+                    atomicOr(reinterpret_cast<uint32_t *>(lb + a), v);
+            }
+            const uint32_t st = __builtin_amdgcn_readlane(q_step, jj);
+            const uint32_t nf = f >= st ? f - st : f + p2 - st;
+            q_first = lane == jj ? nf : q_first;
+        }
+        // small primes: one wave per prime, lane i takes multiples i, i+64, ...
+        for (uint32_t jj = 0; jj < ns_w; ++jj) {
+            const uint32_t p = __builtin_amdgcn_readlane(s_p, jj);
+            const uint32_t f = __builtin_amdgcn_readlane(s_first, jj);
+            const uint32_t o = f + lane * p;
+            if (o < SEG) {
+                const uint32_t v = log_prime(p) << sv_shift(o);
+                for (uint32_t a = sv_addr(o); a < SEG; a += 64 * p)
+                    atomicAdd(reinterpret_cast<uint32_t *>(lb + a), v);
+            }
+            const uint32_t st = __builtin_amdgcn_readlane(s_step, jj);
+            const uint32_t nf = f >= st ? f - st : f + p - st;
+            s_first = lane == jj ? nf : s_first;
+        }
+        // larger primes, carried: walk, then keep the offset in the next segment
 #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-                const uint32_t g = (uint32_t)(j * 4 + g4);
-                const uint32_t T =
-                    low ? 63u - (uint32_t)__clzll((long long)((ybase + 4 * g) | 1)) : Tw;
-                const uint32_t x = vs[g4];
-                const uint32_t F = ((x & 0x7f7f7f7fu) + (128u - T) * 0x01010101u) & 0x80808080u;
-                const uint32_t par = (x & 0x01010101u) << 7;
-                const uint32_t nzb = ~x & 0x80808080u;
-                const uint32_t ngb = ~(F ^ par) & nzb;
-                const uint32_t nzn = ((nzb >> 7) * 0x10204080u) >> 28;
-                const uint32_t ngn = ((ngb >> 7) * 0x10204080u) >> 28;
-                nz |= (uint64_t)nzn << (4 * g);
-                ng |= (uint64_t)ngn << (4 * g);
+        for (int u = 0; u < SV_U; ++u) {
+            const uint32_t p = c_pl[u] & 0xFFFFFFu, v = c_pl[u] >> 24;
+            uint32_t o = c_o[u];
+            for (; o < SEG; o += p)
+                sv_add(lb, o, v);
+            c_o[u] = o - SEG;
+        }
+        // larger primes past the carried ones: offsets from the residues
+        for (uint32_t i = i_carry + tid; i < i_end; i += SIEVE_THREADS) {
+            const uint2 e = b.pres[i];
+            const uint32_t p = e.x, lp = log_prime(p);
+            uint64_t r = (uint64_t)e.y + segbase % p;
+            if (r >= p)
+                r -= p;
+            for (uint64_t o = r ? p - r : 0; o < SEG; o += p)
+                sv_add(lb, (uint32_t)o, lp);
+        }
+        // bucketed primes (> SEG): their hits in this segment, listed per block
+        if (b.n_bucket < b.n_sieve) {
+            const uint32_t e1 = b.bk_start[seg + 1];
+            for (uint32_t k = b.bk_start[seg] + tid; k < e1; k += SIEVE_THREADS) {
+                const uint32_t v = b.bk_buf[k];
+                sv_add(lb, v & (SEG - 1), v >> 17);
             }
         }
-        if (ybase == 0) {  // mu(0..3) = 0, 1, -1, -1
-            nz = (nz & ~0xFull) | 0xEull;
-            ng = (ng & ~0xFull) | 0xCull;
+        // squares p^2 > SQ_LDS_P^2 (> SEG): at most one multiple each in the
+        // segment, listed in its bucket.  Should the bucket have overflowed,
+        // every such prime is checked here instead: f = offset of the block's
+        // first multiple; the segment's first is f - segbase mod p^2, with the
+        // quotient estimated in fp32 (t < 2^31, error < 1) and corrected once.
+        const uint32_t nsq = b.sq_cnt[seg];
+        if (nsq <= SQ_BUCKET) {
+            for (uint32_t k = tid; k < nsq; k += SIEVE_THREADS)
+                sv_square(lb, b.sq_buf[(uint64_t)seg * SQ_BUCKET + k]);
         }
-        nzw[h] = nz;
-        ngw[h] = ng;
-        cnt[h] = (int64_t)__popcll(nz) - 2 * (int64_t)__popcll(ng);
+        for (uint32_t i = b.n_sq_lds + tid; nsq > SQ_BUCKET && i < b.n_sq; i += SIEVE_THREADS) {
+            const uint64_t p = b.pres[i].x;
+            const uint64_t d = p * p;
+            const uint64_t r2 = b.res2[i];
+            const uint64_t f = r2 ? d - r2 : 0;
+            uint64_t o;
+            if (f >= segbase) {
+                o = f - segbase;
+            } else {
+                const uint32_t t = segbase - (uint32_t)f;
+                const uint64_t qt = (uint64_t)((float)t / (float)d);
+                int64_t rem = (int64_t)t - (int64_t)(qt * d);
+                if (rem < 0)
+                    rem += (int64_t)d;
+                else if (rem >= (int64_t)d)
+                    rem -= (int64_t)d;
+                o = rem ? d - (uint64_t)rem : 0;
+            }
+            if (o < SEG)
+                sv_square(lb, (uint32_t)o);
+        }
+        __syncthreads();
+
+        // classify: thread t owns records t + 1024 h of the segment
+        const uint32_t tpar = (Ts & 1u) ? ~0u : 0u;
+        uint64_t packed = 0;
+#pragma unroll
+        for (int h = 0; h < SV_GPT; ++h) {
+            const uint32_t G = tid + (uint32_t)h * SIEVE_THREADS;
+            uint32_t pos, neg;
+            if (first_seg) {
+                const uint32_t yg = (uint32_t)s0 + G * 32;
+                const uint32_t T = yg ? 31u - (uint32_t)__clz((int)yg) : 4u;
+                if (yg == 0)
+                    sv_classify_first(pos, neg);
+                else
+                    sv_classify(lds4[2 * G], lds4[2 * G + 1], (T & 1u) ? ~0u : 0u, pos, neg);
+            } else {
+                sv_classify(lds4[2 * G], lds4[2 * G + 1], tpar, pos, neg);
+            }
+            mpos[j][h] = pos;
+            mneg[j][h] = neg;
+            const int32_t c = __popc(pos) - __popc(neg);  // in [-32, 32]
+            packed |= (uint64_t)(uint32_t)(c + 64) << (16 * h);
+        }
+        // in-wave prefix of the four records' sums (biased fields <= 64 * 96)
+        const uint64_t incl = wave_scan_u64(packed);
+        wex[j] = incl - packed;
+        if (lane == 63) {
+#pragma unroll
+            for (int h = 0; h < SV_GPT; ++h)
+                stot[(j * SV_GPT + h) * NWAVES + wave] =
+                    (int32_t)((incl >> (16 * h)) & 0xFFFFu) - 64 * 64;
+        }
+        __syncthreads();  // the next segment's pattern copy overwrites the bytes
     }
 
-    // fused M(y) prefix: within the segment by a workgroup scan, across
-    // segments by decoupled look-back (Section 4's running sum of mu)
-    int64_t tot0, tot1;
-    const int64_t ex0 = wg_exclusive_scan<SIEVE_THREADS>(cnt[0], wsum, tot0);
-    const int64_t ex1 = wg_exclusive_scan<SIEVE_THREADS>(cnt[1], wsum, tot1);
-    const int64_t T = tot0 + tot1;
-    if (tid < 64) {
+    // exclusive prefix over (segment, record slot, wave) of the wave totals
+    if (wave == 0) {
+        constexpr int E = SV_R * SV_GPT * (int)NWAVES;  // 256 = 4 per lane
+        int32_t v[E / 64], s = 0;
+#pragma unroll
+        for (int e = 0; e < E / 64; ++e) {
+            v[e] = stot[lane * (E / 64) + e];
+            s += v[e];
+        }
+        int32_t x = s;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int32_t t = __shfl_up(x, o, 64);
+            if (lane >= (uint32_t)o)
+                x += t;
+        }
+        int32_t run = x - s;
+#pragma unroll
+        for (int e = 0; e < E / 64; ++e) {
+            stot[lane * (E / 64) + e] = run;
+            run += v[e];
+        }
+        const int64_t T = __shfl(x, 63, 64);  // the group's mu sum
         int64_t before;
-        if (seg == 0) {
+        if (grp == 0) {
             before = *b.carry;
         } else {
-            if (tid == 0)
-                seg_publish(b.seg_state, seg, SEG_AGG, T);
-            before = seg_lookback(b.seg_state, seg);
+            if (lane == 0)
+                seg_publish(b.seg_state, grp, SEG_AGG, T);
+            before = seg_lookback(b.seg_state, grp);
         }
-        if (tid == 0) {
-            seg_publish(b.seg_state, seg, SEG_INCL, before + T);
+        if (lane == 0) {
+            seg_publish(b.seg_state, grp, SEG_INCL, before + T);
             bcast[1] = before;
-            if (seg == b.nseg - 1)
+            if (seg0 + nsegs == b.nseg)
                 *b.carry = before + T;
         }
     }
     __syncthreads();
     const int64_t P = bcast[1];
-    // two 16-byte records per word: {+1 bits | -1 bits << 32, M before}
-    const uint64_t gw0 = (uint64_t)seg * SEG_WORDS + tid;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-        const uint64_t neg = ngw[h], pos = nzw[h] & ~neg;
-        const int64_t mw = P + (h ? tot0 + ex1 : ex0);
-        const int64_t mh = mw + (int64_t)__popc((uint32_t)pos) - (int64_t)__popc((uint32_t)neg);
-        ulonglong2 *r = reinterpret_cast<ulonglong2 *>(
-            b.words + 4 * (gw0 + (uint64_t)h * SIEVE_THREADS));
-        r[0] = make_ulonglong2((pos & 0xFFFFFFFFull) | (neg << 32), (uint64_t)mw);
-        r[1] = make_ulonglong2((pos >> 32) | (neg & 0xFFFFFFFF00000000ull), (uint64_t)mh);
+    for (int j = 0; j < SV_R; ++j) {
+        if ((uint32_t)j >= nsegs)
+            break;
+        const uint64_t rbase = (uint64_t)(seg0 + (uint32_t)j) * SV_GROUPS + tid;
+#pragma unroll
+        for (int h = 0; h < SV_GPT; ++h) {
+            const int32_t inwave =
+                (int32_t)((wex[j] >> (16 * h)) & 0xFFFFu) - 64 * (int32_t)lane;
+            const int64_t m = P + stot[(j * SV_GPT + h) * NWAVES + wave] + inwave;
+            ulonglong2 *r = reinterpret_cast<ulonglong2 *>(
+                b.words + 2 * (rbase + (uint64_t)h * SIEVE_THREADS));
+            *r = make_ulonglong2((uint64_t)mpos[j][h] | ((uint64_t)mneg[j][h] << 32), (uint64_t)m);
+        }
     }
 }
 
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_sieve, dim3(b.nseg), dim3(SIEVE_THREADS), 0, s, b);
+    hipLaunchKernelGGL(k_sieve, dim3((b.nseg + SV_R - 1) / SV_R), dim3(SIEVE_THREADS), 0, s, b);
     return hipGetLastError();
 }
 

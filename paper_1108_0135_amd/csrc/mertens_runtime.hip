@@ -292,25 +292,28 @@ struct SieveState {
 
     // Pattern of the modified sieve for the primes 2, 3, 5, 7, 11, 13 and the
     // squares 4, 9 (period 180180), extended by one segment so a segment's
-    // initial state is one straight copy, in four copies shifted by 0, 4, 8,
-    // 12 bytes so that copy is 16-byte aligned.
+    // initial state is one straight copy, in the sieve's LDS layout (y
+    // offset q of a copy at byte (q & ~31) | (q & 7) << 2 | (q >> 3) & 3),
+    // in eight copies, copy c starting at pattern byte 4c.
     int ensure_pattern()
     {
         if (have_pattern)
             return 0;
         const uint32_t small[6] = {2, 3, 5, 7, 11, 13};
-        // four copies; copy c starts at pattern byte 4c
-        std::vector<uint8_t> pat((size_t)PAT_WORDS * 4 * 4, 0);
-        for (size_t i = 0; i < pat.size(); ++i) {
-            const size_t c = i / ((size_t)PAT_WORDS * 4), j = i % ((size_t)PAT_WORDS * 4);
-            const uint32_t r = (uint32_t)((4 * c + j) % PAT);
-            uint32_t a = 0;
-            for (uint32_t p : small)
-                if (r % p == 0)
-                    a += log_prime_host(p);
-            if (r % 4 == 0 || r % 9 == 0)
-                a |= 0x80u;
-            pat[i] = (uint8_t)a;
+        const size_t copy_bytes = (size_t)PAT_WORDS * 4;
+        std::vector<uint8_t> pat(copy_bytes * PAT_COPIES, 0);
+        for (size_t c = 0; c < PAT_COPIES; ++c) {
+            for (size_t q = 0; q < copy_bytes; ++q) {
+                const uint32_t r = (uint32_t)((4 * c + q) % PAT);
+                uint32_t a = 0;
+                for (uint32_t p : small)
+                    if (r % p == 0)
+                        a += log_prime_host(p);
+                if (r % 4 == 0 || r % 9 == 0)
+                    a |= 0x80u;
+                const size_t at = (q & ~(size_t)31) | ((q & 7) << 2) | ((q >> 3) & 3);
+                pat[c * copy_bytes + at] = (uint8_t)a;
+            }
         }
         RCCHK(ensure(pattern, pat.size()));
         HIPCHK(hipMemcpy(pattern.p, pat.data(), pat.size(), hipMemcpyHostToDevice));
