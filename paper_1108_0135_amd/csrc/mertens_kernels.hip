@@ -1057,6 +1057,9 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
         __syncthreads();  // the next segment's pattern copy overwrites the bytes
     }
 
+    // the zero totals of absent segments (a group shorter than SV_R) were
+    // written after the last barrier
+    __syncthreads();
     // exclusive prefix over (segment, record slot, wave) of the wave totals
     if (wave == 0) {
         constexpr int E = SV_R * SV_GPT * (int)NWAVES;  // 256 = 4 per lane
