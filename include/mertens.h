@@ -75,6 +75,25 @@ int mertens_init(uint64_t u, uint64_t block);
 int mertens_query(const uint64_t *n, size_t count, int64_t *out);
 
 /*
+ * mertens_query_noalloc -- mertens_query for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and errors as
+ * mertens_query, but every device buffer of the call (records, residues,
+ * prime table, pattern copy, per-query arrays) is a piece of one static
+ * 64 MiB device array that each GPU holds from library load until the
+ * process ends; the call makes no hipMalloc or hipFree.  It sweeps in
+ * blocks of at most 2^25 y with the sieve in turn (no graph, no sieve
+ * ahead).  A request that needs more than the scratch holds (roughly, L and
+ * the sieve bound of queries past 10^16) returns MERTENS_ENOMEM with
+ * mertens_last_error() saying so, and nothing is written.  Calls on one
+ * GPU share the scratch and must not overlap (they race; the library is
+ * not thread-safe anyway); it is refused while the serving worker runs.
+ * The A arrays are not kept: mertens_byproducts still refers to the last
+ * mertens_query / mertens_query_wide.  Requires mertens_init.
+ */
+int mertens_query_noalloc(const uint64_t *n, size_t count, int64_t *out);
+
+/*
  * mertens_query_wide -- mertens_query for arguments up to 2^96:
  * n[i] = n_hi[i] 2^64 + n_lo[i] with n_hi[i] < 2^32 (Section 5 computes
  * M(n) for n up to 10^22, past the 64-bit limit, with 128-bit integers).

@@ -76,21 +76,50 @@ double now_s()
 struct DevBuf {
     void *p = nullptr;
     size_t bytes = 0;
+    bool owned = true;  // false: a piece of the no-alloc scratch (never freed)
     template <class T>
     T *as() const { return static_cast<T *>(p); }
     void release()
     {
-        if (p)
+        if (p && owned)
             (void)hipFree(p);
         p = nullptr;
         bytes = 0;
+        owned = true;
     }
 };
+
+// While `on`, every buffer is carved from the no-alloc scratch (the device
+// address of the `scratch` array, 256-byte pieces) instead of hipMalloc.
+struct Arena {
+    uint8_t *base = nullptr;
+    size_t cap = 0, used = 0;
+    bool on = false;
+};
+Arena g_arena;
 
 int ensure(DevBuf &b, size_t bytes)
 {
     if (bytes < 64)
         bytes = 64;
+    if (g_arena.on) {
+        if (b.bytes >= bytes && !b.owned)
+            return 0;
+        const size_t at = (g_arena.used + 255) & ~(size_t)255;
+        if (b.owned && b.p) {
+            set_error_text("no-alloc call would have to free a device buffer");
+            return MERTENS_EINVAL;
+        }
+        if (at > g_arena.cap || bytes > g_arena.cap - at) {
+            set_error_text("the request needs more device memory than the no-alloc scratch holds");
+            return MERTENS_ENOMEM;
+        }
+        b.p = g_arena.base + at;
+        b.bytes = bytes;
+        b.owned = false;
+        g_arena.used = at + bytes;
+        return 0;
+    }
     if (b.bytes >= bytes)
         return 0;
     b.release();
@@ -317,6 +346,16 @@ struct SieveState {
         }
         RCCHK(ensure(pattern, pat.size()));
         HIPCHK(hipMemcpy(pattern.p, pat.data(), pat.size(), hipMemcpyHostToDevice));
+        have_pattern = true;
+        return 0;
+    }
+
+    // The pattern of another state (already on the device), copied on the
+    // device (the no-alloc path takes its copy into the scratch this way).
+    int copy_pattern(const DevBuf &src, hipStream_t s)
+    {
+        RCCHK(ensure(pattern, src.bytes));
+        HIPCHK(hipMemcpyAsync(pattern.p, src.p, src.bytes, hipMemcpyDeviceToDevice, s));
         have_pattern = true;
         return 0;
     }
@@ -897,9 +936,23 @@ struct Ctx {
     hipEvent_t progress_ev = nullptr;
     std::vector<hipEvent_t> events;
     Server srv;
+    bool noalloc = false;  // inside mertens_query_noalloc
 };
 
 Ctx g;
+// ---------------------------------------------------------------------------
+// The no-alloc scratch: one file-scope device array (each device the
+// library runs on holds its own copy until the process ends).  Host code
+// never uses the name `scratch` as an address: mertens_init takes the
+// device address with hipGetSymbolAddress, once per device, and only that
+// address reaches kernels and copies.
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_SCRATCH_BYTES = 64ull << 20;
+constexpr uint64_t NOALLOC_BLOCK = 1ull << 25;  // y per block (16 MiB of records)
+constexpr uint64_t NOALLOC_EV_RING = 16;        // blocks of timing events in the ring
+static __device__ __align__(256) uint8_t scratch[NOALLOC_SCRATCH_BYTES];
+constexpr int MAX_DEVICES = 64;
+uint8_t *g_scratch_dev[MAX_DEVICES] = {nullptr};
 
 // largest interval end: the last block's end and sqrt(b) stay in range
 constexpr uint64_t INTERVAL_NMAX = ~0ull - (1ull << 32) + 1;
@@ -1020,7 +1073,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     // timing events: [0] start, [1]/[2] around finalize, then five per block
     // in a ring of EV_RING blocks (a block's times are added up before its
     // slot is reused)
-    constexpr uint64_t EV_RING = 4096;
+    const uint64_t EV_RING = g.noalloc ? NOALLOC_EV_RING : 4096;
     const uint64_t nring = std::min<uint64_t>(nblocks, EV_RING);
     if (!event_at(3 + 5 * nring) || !slot_events(slots)) {
         set_error_text("hipEventCreate failed");
@@ -1482,11 +1535,103 @@ int mertens_init(uint64_t u, uint64_t block)
     int rc = g.ss.ensure_pattern();
     if (rc == 0)
         rc = g.ss.ensure_primes(1024);
+    // the no-alloc scratch of this device (its address, once per device)
+    // and the timing events a no-alloc call uses, created here
+    if (rc == 0 && g.device >= 0 && g.device < MAX_DEVICES && !g_scratch_dev[g.device]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            set_error("hipGetSymbolAddress(scratch)", e, __FILE__, __LINE__);
+            rc = MERTENS_EIO;
+        } else {
+            g_scratch_dev[g.device] = static_cast<uint8_t *>(ptr);
+        }
+    }
+    if (rc == 0 && (!event_at(3 + 5 * NOALLOC_EV_RING) || !slot_events(1))) {
+        set_error_text("hipEventCreate failed");
+        rc = MERTENS_EIO;
+    }
     if (rc != 0) {
         free_all();
         return rc;
     }
     g.ready = true;
+    return 0;
+}
+
+int mertens_query_noalloc(const uint64_t *n, size_t count, int64_t *out)
+{
+    if (count == 0)
+        return 0;
+    if (!n || !out) {
+        set_error_text("null pointer with count > 0");
+        return MERTENS_EINVAL;
+    }
+    if (!g.ready) {
+        set_error_text("mertens_init has not been called");
+        return MERTENS_ENODEV;
+    }
+    if (g.srv.running) {
+        set_error_text("mertens_query_noalloc cannot run beside the serving worker");
+        return MERTENS_EINVAL;
+    }
+    uint8_t *base = (g.device >= 0 && g.device < MAX_DEVICES) ? g_scratch_dev[g.device] : nullptr;
+    if (!base) {
+        set_error_text("no no-alloc scratch on this device");
+        return MERTENS_ENODEV;
+    }
+    std::vector<uint64_t> ns;
+    std::vector<size_t> where;
+    for (size_t i = 0; i < count; ++i)
+        if (n[i] != 0) {
+            ns.push_back(n[i]);
+            where.push_back(i);
+        }
+    std::vector<int64_t> res;
+    int rc = 0;
+    if (!ns.empty()) {
+        // a fresh sieve state and batch whose every buffer is a piece of the
+        // scratch; the library's own state is put back afterwards
+        SieveState ss_mine;
+        ss_mine.bucket_min = g.ss.bucket_min;
+        Batch bt_mine;
+        std::swap(g.ss, ss_mine);
+        std::swap(g.batch, bt_mine);
+        const Tuning saved = g.tune;
+        const uint64_t saved_block = g.block_req;
+        g.tune.graph = false;
+        g.tune.sieve_ahead = 1;
+        g.tune.progress = 0;
+        g.tune.update_window = 0;
+        if (!g.block_req || g.block_req > NOALLOC_BLOCK)
+            g.block_req = NOALLOC_BLOCK;
+        g.noalloc = true;
+        g_arena = Arena{base, NOALLOC_SCRATCH_BYTES, 0, true};
+        rc = g.ss.copy_pattern(ss_mine.pattern, g.stream);
+        if (rc == 0)
+            rc = run_query(ns, res);
+        // nothing of this call may still run when the next one reuses the scratch
+        const hipError_t e1 = hipStreamSynchronize(g.stream);
+        const hipError_t e2 = hipStreamSynchronize(g.sieve_stream);
+        if (rc == 0 && (e1 != hipSuccess || e2 != hipSuccess)) {
+            set_error("hipStreamSynchronize", e1 != hipSuccess ? e1 : e2, __FILE__, __LINE__);
+            rc = MERTENS_EIO;
+        }
+        g_arena.on = false;
+        g.noalloc = false;
+        g.tune = saved;
+        g.block_req = saved_block;
+        std::swap(g.ss, ss_mine);
+        std::swap(g.batch, bt_mine);
+        ss_mine.release();  // scratch pieces only: nothing is freed
+        bt_mine.release();
+    }
+    if (rc != 0)
+        return rc;
+    for (size_t i = 0; i < count; ++i)
+        out[i] = 0;
+    for (size_t j = 0; j < where.size(); ++j)
+        out[where[j]] = res[j];
     return 0;
 }
 

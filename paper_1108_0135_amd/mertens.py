@@ -32,6 +32,7 @@ _P = ctypes.POINTER
 _sig = {
     "mertens_init": ([_u64, _u64], ctypes.c_int),
     "mertens_query": ([_P(_u64), _sz, _P(_i64)], ctypes.c_int),
+    "mertens_query_noalloc": ([_P(_u64), _sz, _P(_i64)], ctypes.c_int),
     "mertens_byproducts": ([_sz, _P(_i64), _sz, _P(_sz)], ctypes.c_int),
     "mertens_query_wide": ([_P(_u64), _P(_u64), _sz, _P(_i64)], ctypes.c_int),
     "mertens_set_stream": ([ctypes.c_void_p], ctypes.c_int),
@@ -98,6 +99,14 @@ def query(ns) -> np.ndarray:
     arr = np.ascontiguousarray(np.asarray(ns, dtype=np.uint64).reshape(-1))
     out = np.zeros(arr.size, dtype=np.int64)
     _check(_lib.mertens_query(_u64p(arr), arr.size, _i64p(out)), "mertens_query")
+    return out
+
+
+def query_noalloc(ns) -> np.ndarray:
+    """M(n) like query(), through the entry point that allocates no device memory."""
+    arr = np.ascontiguousarray(np.asarray(ns, dtype=np.uint64).reshape(-1))
+    out = np.zeros(arr.size, dtype=np.int64)
+    _check(_lib.mertens_query_noalloc(_u64p(arr), arr.size, _i64p(out)), "mertens_query_noalloc")
     return out
 
 
