@@ -21,6 +21,8 @@ Other workloads (``--workload``), reported separately:
            from the printed extreme on, and the extremes of M(n)/sqrt(n)
   wide     M(10^20) past the 64-bit limit (about 100 s per step; one timed
            step and no warmup unless asked)
+  window   the dense window: 1024 n_i = n0 + 997 i near 1.2e19 as one shared
+           sweep (one timed step), against the first member alone
 """
 from __future__ import annotations
 
@@ -454,6 +456,52 @@ def workload_interval(args, mt) -> dict:
     }
 
 
+def workload_window(args, mt) -> dict:
+    """The dense window: 1024 n_i = n0 + 997 i (n0 seeded in [1e18, 1.8e19]) as
+    one shared sweep (one keyed group of the distinct (x, floor(n_i/x))),
+    against the first member alone.  The first eight members' differences
+    are the oracle's (stored expected values); member 0 must equal its
+    value alone."""
+    import torch
+    from paper_1108_0135_amd import inputs
+    gold = json.load(open(os.path.join(ROOT, "tests", "golden", "golden.json")))["window1e19_diffs"]
+    ns = [int(v) for v in inputs.dense_window(seed=0, count=1024)]
+    if ns[:8] != gold["n"]:
+        raise RuntimeError("window inputs differ from the stored ones")
+    mt.init(0, 0)
+    mt.set_param("progress", 512)  # a line every 512 blocks on stderr
+    progress("dense window: member 0 alone")
+    t0 = time.perf_counter()
+    alone = int(mt.query([ns[0]])[0])
+    t_alone = time.perf_counter() - t0
+    st_alone = mt.stats()
+    progress(f"dense window: 1024 members, one sweep (member 0 alone took {t_alone:.1f} s)")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    got = [int(v) for v in mt.query(ns)]
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = mt.stats()
+    if got[0] != alone or [got[i + 1] - got[i] for i in range(7)] != gold["diffs"]:
+        raise RuntimeError("dense window results wrong")
+    return {"metric": METRIC, "value": len(ns) / dt, "unit": "queries/s", "n_gpus": 1,
+            "steps": 1, "warmup": 0, "ms_per_step": dt * 1e3, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "u64", "data": "synthetic",
+            "config": {"workload": "dense window: 1024 n_i = n0 + 997 i, n0 seeded in [1e18, 1.8e19] "
+                                   "(seed 0), one shared sweep; first 8 differences against the oracle",
+                       "n0": ns[0], "u": st["u"], "blocks": st["blocks"],
+                       "entries": st["sum_L"], "parallelism": "1 GPU"},
+            "sieved_y_per_s": st["sieved_y"] / dt,
+            "pairs": {"run_length": st["rl_quotients"], "explicit_k": st["k_quotients"]},
+            "pairs_per_s": (st["rl_quotients"] + st["k_quotients"]) / dt,
+            "member0_alone_s": t_alone, "member0_alone_blocks": st_alone["blocks"],
+            "one_at_a_time_s_estimated": 1024 * t_alone,
+            "speedup_vs_one_at_a_time_estimated": 1024 * t_alone / dt,
+            "kernel_ms": {k: st[k] for k in ("ms_sieve", "ms_prep", "ms_update", "ms_finalize",
+                                             "ms_total")},
+            "tuning": mt.tuning()}
+
+
 def workload_wide(args, mt) -> dict:
     """M(10^20) through mertens_query_wide (Table 1), one query per step."""
     import torch
@@ -511,7 +559,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=None,
                     help="untimed warmup steps (default 1; 0 for the wide workload)")
     ap.add_argument("--workload",
-                    choices=["default", "batched", "serving", "interval", "wide", "copy"],
+                    choices=["default", "batched", "serving", "interval", "wide", "window",
+                             "copy"],
                     default="default")
     ap.add_argument("--rate", type=float, default=10.0)
     ap.add_argument("--count", type=int, default=48)
@@ -549,6 +598,8 @@ def main() -> int:
                 line["cpu_baseline"] = cpu_baseline_interval()
         elif args.workload == "wide":
             line = workload_wide(args, mt)
+        elif args.workload == "window":
+            line = workload_window(args, mt)
         elif args.workload == "copy":
             line = workload_copy(args, mt)
         else:

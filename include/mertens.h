@@ -180,6 +180,9 @@ int mertens_set_stream(void *hip_stream);
  *                 their pairs instead (default 0: never)
  *   "waves_per_cu" persistent update grid size per compute unit (default 12,
  *                 the waves of three resident workgroups)
+ *   "block_auto"  y-block length when mertens_init got block = 0 (a multiple
+ *                 of 2^17 in [2^17, 2^31]; default 2^30, or the whole sweep
+ *                 when it is shorter)
  *   "graph"       1: replay one captured hipGraph of the per-block kernel
  *                 sequence; 0: direct launches (default)
  *   "sieve_ahead" direct launches: most blocks sieved ahead of the update on
@@ -213,8 +216,12 @@ int mertens_set_stream(void *hip_stream);
 int mertens_set_param(const char *key, double value);
 
 /*
- * mertens_get_param -- the current value of a mertens_set_param key (the
- * defaults until changed; mertens_init restores them) into *value.
+ * mertens_get_param -- the current value of a mertens_set_param key into
+ * *value, and "tuned": 1 when mertens_init applied the stored autotuner
+ * choice (tuned_<arch>.json next to the library, taken on the kernel
+ * sources this library was built from; the environment variable
+ * MERTENS_TUNED=0 skips it), else 0.  mertens_init restores the built-in
+ * defaults, then applies that file.
  * Returns 0, or MERTENS_EINVAL for an unknown key or a NULL pointer.
  */
 int mertens_get_param(const char *key, double *value);

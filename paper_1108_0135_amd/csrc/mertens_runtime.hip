@@ -16,6 +16,8 @@
 #include "mertens.h"
 #include "mertens_internal.h"
 
+#include <dlfcn.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -207,7 +209,15 @@ struct Tuning {
     // stderr (for sweeps that run many minutes)
     uint64_t progress = 0;
     bool graph = false;  // replay one captured hipGraph per block
+    uint64_t block_auto = 1ull << 30;  // block length when mertens_init gets block = 0
 };
+
+#ifndef MERTENS_KERNEL_SHA256
+#define MERTENS_KERNEL_SHA256 ""
+#endif
+#ifndef MERTENS_ARCH_NAME
+#define MERTENS_ARCH_NAME "gfx950"
+#endif
 
 // Primes p in [5, limit] (limit <= 2^32) into pr, ascending: segmented
 // Eratosthenes over odd numbers, 2^19 of them per segment, crossed off by the
@@ -363,7 +373,7 @@ struct SieveState {
     // record buffers for `slots` blocks of length B (a ring: block b uses
     // slot b mod slots) and their per-slot device parameters, followed by
     // the parameters of up to MAX_WINDOWS update windows
-    static constexpr uint32_t MAX_WINDOWS = 64;
+    static constexpr uint32_t MAX_WINDOWS = 1024;
     uint32_t slots = 1;
     uint64_t slot_words = 0;  // uint64 per slot
 
@@ -857,12 +867,12 @@ uint32_t update_grid(int ncu, const Tuning &t)
     return (uint32_t)std::max(1, ncu * (int)t.waves_per_cu / (UPD_THREADS / 64));
 }
 
-uint64_t choose_block(uint64_t req, uint64_t ymax)
+uint64_t choose_block(uint64_t req, uint64_t ymax, uint64_t cap = 1ull << 30)
 {
     if (req)
         return req;
     const uint64_t need = (ymax / SEG + 1) * SEG;
-    return std::min<uint64_t>(need, 1ull << 30);
+    return std::min<uint64_t>(need, cap);
 }
 
 // ---------------------------------------------------------------------------
@@ -912,6 +922,10 @@ struct Server {
     uint64_t blocks_run = 0;
 };
 
+constexpr size_t SERVE_CAPACITY_DEFAULT = 4096;
+constexpr uint64_t SERVE_X_BUDGET_DEFAULT = 1ull << 26;
+constexpr uint64_t SERVE_SHORT_BLOCKS_DEFAULT = 4;
+
 struct Ctx {
     bool ready = false;
     int device = 0;
@@ -922,9 +936,9 @@ struct Ctx {
     std::vector<hipEvent_t> sieved_ev, updated_ev;  // per record slot
     uint64_t u_req = 0, block_req = 0;
     Tuning tune;
-    size_t serve_capacity = 4096;
-    uint64_t serve_x_budget = 1ull << 26;  // x entries in flight (64 B each)
-    uint64_t serve_short_blocks = 4;       // requests needing at most this many blocks
+    size_t serve_capacity = SERVE_CAPACITY_DEFAULT;
+    uint64_t serve_x_budget = SERVE_X_BUDGET_DEFAULT;  // x entries in flight (64 B each)
+    uint64_t serve_short_blocks = SERVE_SHORT_BLOCKS_DEFAULT;  // requests needing at most this many blocks
     SieveState ss;
     Batch batch;
     DevBuf iv_part, iv_small, iv_vals;  // interval sweep: partial extremes, scalars, values
@@ -937,9 +951,11 @@ struct Ctx {
     std::vector<hipEvent_t> events;
     Server srv;
     bool noalloc = false;  // inside mertens_query_noalloc
+    bool tuned = false;    // the stored tuning file was applied by mertens_init
 };
 
 Ctx g;
+
 // ---------------------------------------------------------------------------
 // The no-alloc scratch: one file-scope device array (each device the
 // library runs on holds its own copy until the process ends).  Host code
@@ -1064,7 +1080,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     const uint64_t ymax = bt.ymax_all;
     RCCHK(g.ss.ensure_primes(std::max<uint64_t>(ceil_sqrt_host(ymax), 1024)));
     RCCHK(g.ss.ensure_pattern());
-    const uint64_t B = choose_block(g.block_req, ymax);
+    const uint64_t B = choose_block(g.block_req, ymax, g.tune.block_auto);
     const uint64_t nblocks = ymax / B + 1;
     const uint32_t slots = g.tune.graph ? 1u : record_slots(B, nblocks);
     RCCHK(g.ss.ensure_blocks(B, slots));
@@ -1507,6 +1523,69 @@ void serve_stop()
 // ======================================================================
 extern "C" {
 
+// The autotuner's choice: tuned_<arch>.json next to this library, applied
+// when its "source_sha256" equals the hash of the kernel sources compiled
+// in (a file measured on other kernels is ignored); MERTENS_TUNED=0 skips
+// it.  Only the flat "params" object is read ("key": number pairs), each
+// through mertens_set_param (a value it refuses is skipped).
+static void load_tuned()
+{
+    g.tuned = false;
+    const char *env = getenv("MERTENS_TUNED");
+    if ((env && !strcmp(env, "0")) || !MERTENS_KERNEL_SHA256[0])
+        return;
+    Dl_info info;
+    if (!dladdr(reinterpret_cast<void *>(&mertens_init), &info) || !info.dli_fname)
+        return;
+    std::string path(info.dli_fname);
+    path = path.substr(0, path.rfind('/') + 1) + "tuned_" MERTENS_ARCH_NAME ".json";
+    FILE *f = fopen(path.c_str(), "rb");
+    if (!f)
+        return;
+    std::string txt;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0 && txt.size() < (1u << 20))
+        txt.append(buf, got);
+    fclose(f);
+    auto string_after = [&](const char *key, size_t from, size_t &end) -> std::string {
+        const size_t k = txt.find(key, from);
+        if (k == std::string::npos)
+            return std::string();
+        const size_t a = txt.find('"', txt.find(':', k + strlen(key)) + 1);
+        const size_t b = a == std::string::npos ? a : txt.find('"', a + 1);
+        if (b == std::string::npos)
+            return std::string();
+        end = b + 1;
+        return txt.substr(a + 1, b - a - 1);
+    };
+    size_t pos = 0;
+    if (string_after("\"source_sha256\"", 0, pos) != MERTENS_KERNEL_SHA256)
+        return;
+    size_t p = txt.find("\"params\"");
+    p = p == std::string::npos ? p : txt.find('{', p);
+    if (p == std::string::npos)
+        return;
+    ++p;
+    for (;;) {
+        const size_t a = txt.find_first_not_of(" \t\r\n,", p);
+        if (a == std::string::npos || txt[a] != '"')
+            break;
+        const size_t b = txt.find('"', a + 1);
+        const size_t c = b == std::string::npos ? b : txt.find(':', b);
+        if (c == std::string::npos)
+            break;
+        const std::string key = txt.substr(a + 1, b - a - 1);
+        char *endp = nullptr;
+        const double v = strtod(txt.c_str() + c + 1, &endp);
+        if (endp == txt.c_str() + c + 1)
+            break;
+        (void)mertens_set_param(key.c_str(), v);
+        p = (size_t)(endp - txt.c_str());
+    }
+    g.tuned = true;
+}
+
 int mertens_init(uint64_t u, uint64_t block)
 {
     if (block != 0 && (block < SEG || block % SEG != 0 || block > (1ull << 31))) {
@@ -1532,6 +1611,10 @@ int mertens_init(uint64_t u, uint64_t block)
     g.block_req = block;
     g.tune = Tuning();
     g.ss.bucket_min = SieveState().bucket_min;
+    g.serve_capacity = SERVE_CAPACITY_DEFAULT;
+    g.serve_x_budget = SERVE_X_BUDGET_DEFAULT;
+    g.serve_short_blocks = SERVE_SHORT_BLOCKS_DEFAULT;
+    load_tuned();
     int rc = g.ss.ensure_pattern();
     if (rc == 0)
         rc = g.ss.ensure_primes(1024);
@@ -1793,7 +1876,7 @@ int mertens_interval(uint64_t a, uint64_t b, const int64_t *m_a, int64_t *m_b, u
     const uint64_t nblocks = (b - start) / B + 1;
     // timing events: [0] start, [1] end, then seven per block in a ring of
     // EV_RING blocks (a block's times are added up before its slot is reused)
-    constexpr uint64_t EV_RING = 4096;
+    const uint64_t EV_RING = g.noalloc ? NOALLOC_EV_RING : 4096;
     const uint64_t nring = std::min<uint64_t>(nblocks, EV_RING);
     if (!event_at(2 + 7 * nring)) {
         set_error_text("hipEventCreate failed");
@@ -2021,6 +2104,11 @@ int mertens_set_param(const char *key, double value)
         if (!(value >= 4 && value <= 64))
             return MERTENS_EINVAL;
         g.tune.waves_per_cu = (uint32_t)value;
+    } else if (!strcmp(key, "block_auto")) {
+        if (!(value >= SEG && value <= 2147483648.0) || value != std::floor(value) ||
+            ((uint64_t)value) % SEG != 0)
+            return MERTENS_EINVAL;
+        g.tune.block_auto = (uint64_t)value;
     } else if (!strcmp(key, "serve_capacity")) {
         if (!(value >= 1 && value <= (1 << 20)))
             return MERTENS_EINVAL;
@@ -2073,6 +2161,10 @@ int mertens_get_param(const char *key, double *value)
         *value = t.sieve_ahead;
     else if (!strcmp(key, "waves_per_cu"))
         *value = t.waves_per_cu;
+    else if (!strcmp(key, "block_auto"))
+        *value = (double)t.block_auto;
+    else if (!strcmp(key, "tuned"))
+        *value = g.tuned ? 1.0 : 0.0;
     else if (!strcmp(key, "serve_capacity"))
         *value = (double)g.serve_capacity;
     else if (!strcmp(key, "serve_short_blocks"))

@@ -175,8 +175,8 @@ def set_param(key: str, value: float) -> None:
     _check(_lib.mertens_set_param(key.encode(), float(value)), f"mertens_set_param({key})")
 
 
-TUNING_KEYS = ["u_scale", "beta", "ychunk", "kchunk", "kbal", "waves_per_cu", "graph",
-               "sieve_ahead", "update_window", "bucket_min", "rl_fast", "wide_bits"]
+TUNING_KEYS = ["tuned", "u_scale", "beta", "ychunk", "kchunk", "kbal", "waves_per_cu", "graph",
+               "block_auto", "sieve_ahead", "update_window", "bucket_min", "rl_fast", "wide_bits"]
 
 
 def get_param(key: str) -> float:

@@ -140,6 +140,8 @@ def test_n1e12_and_byproducts(mt):
     (10**8, 1 << 26, {"kbal": 64}),
     # every prime above 2^17 through per-segment buckets
     (10**8, 1 << 24, {"bucket_min": 1}),
+    # the tested run-length path with a small update grid
+    (3 * 10**7, 1 << 20, {"rl_fast": 0, "waves_per_cu": 4}),
 ])
 def test_n1e12_invariance(mt, u, block, params):
     g = GOLDEN["n1e12"]
