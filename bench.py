@@ -14,9 +14,9 @@ timed on the host (one core, and one process per core).
 Other workloads (``--workload``), reported separately:
   batched  256 n log-uniform in [1e13, 1e17] (seed 0) plus 1e16 and 1e17,
            one shared sweep vs. one query at a time
-  serving  Poisson arrivals (``--rate`` q/s, ``--count`` queries, n
-           log-uniform in [1e10, 1e18]) through mertens_submit/poll vs. a
-           one-at-a-time FIFO server; p50/p99 latency and queries/s
+  serving  Poisson arrivals at each of ``--rates`` q/s (``--count`` queries,
+           n log-uniform in [1e10, 1e18]) through mertens_submit/poll vs. a
+           one-at-a-time FIFO server; p50/p99 latency and queries/s per rate
   interval Section 6 localization: M(n) for every n of a 2^35-wide interval
            from the printed extreme on, and the extremes of M(n)/sqrt(n)
   wide     M(10^20) past the 64-bit limit (about 100 s per step; one timed
@@ -324,27 +324,9 @@ def workload_batched(args, mt) -> dict:
             "config": {"workload": BATCHED_WORKLOAD}, "tuning": mt.tuning(), **res}
 
 
-def workload_serving(args, mt) -> dict:
-    import numpy as np
-    from paper_1108_0135_amd import inputs
-    times, ns = inputs.poisson_trace(seed=0, rate=args.rate, count=args.count)
-    ns = [int(v) for v in ns]
-    # reference values and one-at-a-time service times (FIFO server)
-    mt.init(0, 0)
-    mt.query([10**12])
-    service, ref = [], []
-    for n in ns:
-        t0 = time.perf_counter()
-        ref.append(int(mt.query([n])[0]))
-        service.append(time.perf_counter() - t0)
-    finish, fifo_lat = 0.0, []
-    for a, s in zip(times, service):
-        start = max(a, finish)
-        finish = start + s
-        fifo_lat.append(finish - a)
-    fifo_makespan = finish - times[0]
-    mt.shutdown()
-    # serving path: submit at the arrival times, poll until all are done
+def _serve_trace(mt, times, ns):
+    """Submit each n at its arrival time, poll until every result is in;
+    returns (results, latencies, makespan)."""
     mt.init(0, 0)
     t_base = time.perf_counter()
     pending, lat, got = {}, [0.0] * len(ns), [None] * len(ns)
@@ -365,16 +347,58 @@ def workload_serving(args, mt) -> dict:
         time.sleep(0.001)
     makespan = time.perf_counter() - t_base
     mt.shutdown()
-    if got != ref:
-        raise RuntimeError("served results differ from one-at-a-time results")
+    return got, lat, makespan
+
+
+def workload_serving(args, mt) -> dict:
+    """Poisson arrivals at each rate of --rates (the same --count values of n,
+    log-uniform in [1e10, 1e18], seed 0) through mertens_submit/poll, against
+    a one-at-a-time FIFO server whose service times are each n's measured
+    time alone.  Results must equal the one-at-a-time values."""
+    import numpy as np
+    from paper_1108_0135_amd import inputs
+    rates = [float(r) for r in args.rates.split(",")]
+    _, ns0 = inputs.poisson_trace(seed=0, rate=rates[0], count=args.count)
+    ns = [int(v) for v in ns0]
+    progress(f"serving: {len(ns)} values of n one at a time (FIFO service times)")
+    mt.init(0, 0)
+    mt.query([10**12])
+    service, ref = [], []
+    for k, n in enumerate(ns):
+        t0 = time.perf_counter()
+        ref.append(int(mt.query([n])[0]))
+        service.append(time.perf_counter() - t0)
+        if k % 25 == 24:
+            progress(f"one at a time: {k + 1} of {len(ns)}")
+    mt.shutdown()
     p = lambda v, q: float(np.percentile(v, q))
-    return {"metric": METRIC, "value": len(ns) / makespan, "unit": "queries/s", "n_gpus": 1,
+    sweep = []
+    for rate in rates:
+        times, ns_r = inputs.poisson_trace(seed=0, rate=rate, count=args.count)
+        if [int(v) for v in ns_r] != ns:
+            raise RuntimeError("the trace's n depend on the rate")
+        finish, fifo_lat = 0.0, []
+        for a_t, s_t in zip(times, service):
+            start = max(a_t, finish)
+            finish = start + s_t
+            fifo_lat.append(finish - a_t)
+        fifo_makespan = finish - times[0]
+        progress(f"serving at {rate:g} q/s")
+        got, lat, makespan = _serve_trace(mt, times, ns)
+        if got != ref:
+            raise RuntimeError(f"served results differ from one-at-a-time results at {rate} q/s")
+        sweep.append({"rate": rate,
+                      "served": {"qps": len(ns) / makespan, "p50_s": p(lat, 50),
+                                 "p99_s": p(lat, 99)},
+                      "fifo_plain": {"qps": len(ns) / fifo_makespan, "p50_s": p(fifo_lat, 50),
+                                     "p99_s": p(fifo_lat, 99)}})
+    best = max(sweep, key=lambda r: r["served"]["qps"])
+    return {"metric": METRIC, "value": best["served"]["qps"], "unit": "queries/s", "n_gpus": 1,
             "higher_is_better": True, "dtype": "u64", "data": "synthetic",
-            "config": {"workload": f"Poisson {args.rate} q/s, {args.count} queries, n log-uniform "
-                                   "in [1e10,1e18], seed 0"},
-            "served": {"qps": len(ns) / makespan, "p50_s": p(lat, 50), "p99_s": p(lat, 99)},
-            "fifo_plain": {"qps": len(ns) / fifo_makespan, "p50_s": p(fifo_lat, 50),
-                           "p99_s": p(fifo_lat, 99)}}
+            "config": {"workload": f"Poisson arrivals at {args.rates} q/s, {args.count} queries each, "
+                                   "n log-uniform in [1e10,1e18], seed 0",
+                       "parallelism": "1 GPU"},
+            "one_at_a_time_total_s": float(sum(service)), "sweep": sweep}
 
 
 IV_WIDTH = 2**35  # interval workload: [EXTREME_N, EXTREME_N + 2^35]
@@ -469,7 +493,10 @@ def workload_window(args, mt) -> dict:
     if ns[:8] != gold["n"]:
         raise RuntimeError("window inputs differ from the stored ones")
     mt.init(0, 0)
-    mt.set_param("progress", 512)  # a line every 512 blocks on stderr
+    # a line every 64 blocks on stderr, and per 2^26-y window of block 0
+    # (which holds most of the work)
+    mt.set_param("progress", 64)
+    mt.set_param("update_window", 26)
     progress("dense window: member 0 alone")
     t0 = time.perf_counter()
     alone = int(mt.query([ns[0]])[0])
@@ -562,8 +589,9 @@ def main() -> int:
                     choices=["default", "batched", "serving", "interval", "wide", "window",
                              "copy"],
                     default="default")
-    ap.add_argument("--rate", type=float, default=10.0)
-    ap.add_argument("--count", type=int, default=48)
+    ap.add_argument("--rates", default="10,30,100,300,1000",
+                    help="serving: comma-separated arrival rates (q/s)")
+    ap.add_argument("--count", type=int, default=200, help="serving: arrivals per rate")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--in-turn", action="store_true",

@@ -719,10 +719,11 @@ __device__ inline int64_t seg_lookback(const uint64_t *st, uint32_t seg)
 // word within its group, so it advances by a constant 64p bytes.
 //
 // Each workgroup sieves SV_R consecutive segments (a group of segments
-// claimed in ticket order) and carries the per-prime offsets from one
-// segment to the next: the small primes' (one wavefront per prime) in
-// lane-distributed registers, the first SV_U * SIEVE_THREADS larger primes'
-// (one lane per prime) in per-thread registers.  The classified masks of
+// claimed in ticket order) with one residue per prime: the small primes'
+// and small squares' (one wavefront per prime) first multiples in every
+// segment of the group are set up at the start in lane-distributed
+// registers; the first SV_U * SIEVE_THREADS larger primes (one lane per
+// prime) carry their next offset in per-thread registers.  The classified masks of
 // all SV_R segments stay in registers until the group's M(y) prefix is
 // known (workgroup scan plus decoupled look-back over earlier groups);
 // then whole 16-byte records are written.
@@ -831,34 +832,46 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
     const uint32_t nsegs = b.nseg - seg0 < (uint32_t)SV_R ? b.nseg - seg0 : (uint32_t)SV_R;
     const uint32_t segbase0 = seg0 * SEG;  // < 2^31
 
-    // ---- carried offsets (first multiple in the current segment)
+    // ---- first multiple in each of the group's segments
     // squares p^2, p <= SQ_LDS_P (index < n_sq_lds): wave w, lane j holds index w + 16 j
-    uint32_t q_p2 = 0, q_first = 0, q_step = 0;
+    uint32_t q_p2 = 0, q_first[SV_R];
     {
         const uint32_t i = wave + NWAVES * lane;
+        uint32_t f = 0, st = 0;
         if (i < b.n_sq_lds) {
             const uint32_t p = b.pres[i].x;
             q_p2 = p * p;  // < 2^21
             uint32_t r = (uint32_t)b.res2[i] + segbase0 % q_p2;
             if (r >= q_p2)
                 r -= q_p2;
-            q_first = r ? q_p2 - r : 0;
-            q_step = SEG % q_p2;
+            f = r ? q_p2 - r : 0;
+            st = SEG % q_p2;
+        }
+#pragma unroll
+        for (int j = 0; j < SV_R; ++j) {  // next segment: (f - SEG) mod p^2
+            q_first[j] = f;
+            f = f >= st ? f - st : f + q_p2 - st;
         }
     }
     // small primes (index in [FIRST_SIEVED, n_small)): wave w, lane j holds
     // index FIRST_SIEVED + w + 16 j
-    uint32_t s_p = 0, s_first = 0, s_step = 0;
+    uint32_t s_p = 0, s_first[SV_R];
     {
         const uint32_t i = FIRST_SIEVED + wave + NWAVES * lane;
+        uint32_t f = 0, st = 0;
         if (i < b.n_small) {
             const uint32_t p = b.pres[i].x;
             s_p = p;
             uint32_t r = b.pres[i].y + segbase0 % p;  // both < p < SMALL_P
             if (r >= p)
                 r -= p;
-            s_first = r ? p - r : 0;
-            s_step = SEG % p;
+            f = r ? p - r : 0;
+            st = SEG % p;
+        }
+#pragma unroll
+        for (int j = 0; j < SV_R; ++j) {
+            s_first[j] = f;
+            f = f >= st ? f - st : f + s_p - st;
         }
     }
     const uint32_t nq_w = b.n_sq_lds > wave ? (b.n_sq_lds - wave + NWAVES - 1) / NWAVES : 0u;
@@ -919,49 +932,43 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
         // the segment is a whole run of 32-byte groups of it
         const uint4 *src = reinterpret_cast<const uint4 *>(
             b.pat32 + (size_t)((po >> 2) & 7u) * PAT_WORDS + (size_t)(po >> 5) * 8);
-        for (uint32_t q = tid; q < SEG / 16; q += SIEVE_THREADS) {
-            uint4 v = src[q];
-            uint32_t T = Ts;
+        // the next load in flight while one is biased and stored (8 uint4 per thread)
+        const uint32_t bias_s = (64u - Ts) * 0x01010101u;
+        constexpr int PER = (int)(SEG / 16 / SIEVE_THREADS);
+        uint4 cur = src[tid];
+#pragma unroll
+        for (int k = 0; k < PER; ++k) {
+            const uint32_t q = tid + (uint32_t)k * SIEVE_THREADS;
+            const uint4 nxt = (k + 1 < PER) ? src[q + SIEVE_THREADS] : cur;
+            uint32_t bias = bias_s;
             if (first_seg) {
                 const uint32_t yg = (uint32_t)s0 + (q >> 1) * 32;
-                T = yg ? 31u - (uint32_t)__clz((int)yg) : 4u;
+                bias = (64u - (yg ? 31u - (uint32_t)__clz((int)yg) : 4u)) * 0x01010101u;
             }
-            const uint32_t bias = (64u - T) * 0x01010101u;
-            v.x += bias;
-            v.y += bias;
-            v.z += bias;
-            v.w += bias;
-            lds4[q] = v;
+            lds4[q] = make_uint4(cur.x + bias, cur.y + bias, cur.z + bias, cur.w + bias);
+            cur = nxt;
         }
         __syncthreads();
 
         // squares p^2 <= SQ_LDS_P^2: one wave per prime, lane i takes multiple i
         for (uint32_t jj = 0; jj < nq_w; ++jj) {
             const uint32_t p2 = __builtin_amdgcn_readlane(q_p2, jj);
-            const uint32_t f = __builtin_amdgcn_readlane(q_first, jj);
-            const uint32_t o = f + lane * p2;
+            const uint32_t o = __builtin_amdgcn_readlane(q_first[j], jj) + __umul24(lane, p2);
             if (o < SEG) {
                 const uint32_t v = 0x80u << sv_shift(o);
                 for (uint32_t a = sv_addr(o); a < SEG; a += 64 * p2)
                     atomicOr(reinterpret_cast<uint32_t *>(lb + a), v);
             }
-            const uint32_t st = __builtin_amdgcn_readlane(q_step, jj);
-            const uint32_t nf = f >= st ? f - st : f + p2 - st;
-            q_first = lane == jj ? nf : q_first;
         }
         // small primes: one wave per prime, lane i takes multiples i, i+64, ...
         for (uint32_t jj = 0; jj < ns_w; ++jj) {
             const uint32_t p = __builtin_amdgcn_readlane(s_p, jj);
-            const uint32_t f = __builtin_amdgcn_readlane(s_first, jj);
-            const uint32_t o = f + lane * p;
+            const uint32_t o = __builtin_amdgcn_readlane(s_first[j], jj) + __umul24(lane, p);
             if (o < SEG) {
                 const uint32_t v = log_prime(p) << sv_shift(o);
                 for (uint32_t a = sv_addr(o); a < SEG; a += 64 * p)
                     atomicAdd(reinterpret_cast<uint32_t *>(lb + a), v);
             }
-            const uint32_t st = __builtin_amdgcn_readlane(s_step, jj);
-            const uint32_t nf = f >= st ? f - st : f + p - st;
-            s_first = lane == jj ? nf : s_first;
         }
         // larger primes, carried: walk, then keep the offset in the next segment
 #pragma unroll
