@@ -1570,13 +1570,27 @@ constexpr uint32_t RL_ENT_CAP = 3072;   // 1024 of any 4096 consecutive y are mu
 // Below this m the rounded-up reciprocal gives exact floors with no test.
 constexpr double RL_M_EXACT = 281474976710656.0;  // 2^48
 
+// 1/y within one unit in the last place: the hardware estimate refined by
+// two fused Newton steps (e = 1 - y r, r += r e).  From an estimate within
+// 2^-20 the first step leaves a relative error near 2^-40, the second only
+// its final rounding (half a unit) plus terms near 2^-80.
+__device__ inline double rcp_1ulp(double y)
+{
+    double r = __builtin_amdgcn_rcp(y);
+    double e = fma(-y, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-y, r, 1.0);
+    return fma(r, e, r);
+}
+
 // One pass of RL_XS x (m as fp64 in mf, NaN past the tile's end) over the
 // compacted entries.
-// * FAST (every m < 2^48, every y <= Y): r' = RN(1/y) raised by 4 ulps lies
-//   in [(1/y)(1 + 2^-52), (1/y)(1 + 2^-48.9)], so qd = RN(m r') lies in
-//   (m/y, (m/y)(1 + 2^-48.8)): never below m/y, and above the next integer
-//   only if m/y were within (m/y) 2^-48.8 < 1/y of it, which m mod y >= 0
-//   rules out.  floor(qd) = floor(m/y) exactly: three fp64 ops per pair.
+// * FAST (every m < 2^48, every y <= Y): with r within one ulp of 1/y
+//   (rcp_1ulp), r' = r raised by 4 ulps lies in [(1/y)(1 + 2^-52),
+//   (1/y)(1 + 2^-49.6)], so qd = RN(m r') lies in [m/y, (m/y)(1 + 2^-49.5)]:
+//   never below m/y, and above the next integer only if m/y were within
+//   (m/y) 2^-49.5 < 1/y of it, which m mod y >= 0 rules out.  floor(qd) =
+//   floor(m/y) exactly: three fp64 ops per pair.
 // * otherwise: qh = m/y - 1/2 rounded once (fma); t = rint(qh) is
 //   floor(m/y) unless qh lies within QEPS of a half-integer, which the
 //   running max of |qh - t| detects; such entries redo the RL_XS pairs with
@@ -1595,14 +1609,14 @@ __device__ inline void rl_pass(const uint16_t *ent, uint32_t total, uint32_t wb0
         const uint32_t e = ent[t];
         const uint32_t y = wb0 + (e & 0x0FFFu);
         const double sg = (e & 0x8000u) ? -1.0 : 1.0;
-        const double r = 1.0 / (double)y;
         if (MODE == RL_FAST) {
-            const double ru = __longlong_as_double(__double_as_longlong(r) + 4);
+            const double ru = __longlong_as_double(__double_as_longlong(rcp_1ulp((double)y)) + 4);
 #pragma unroll
             for (int i = 0; i < RL_XS; ++i)
                 acc[i] = fma(sg, floor(mf[i] * ru), acc[i]);
             continue;
         }
+        const double r = 1.0 / (double)y;
         double dmax = 0.0;
 #pragma unroll
         for (int i = 0; i < RL_XS; ++i) {
@@ -1918,6 +1932,30 @@ __device__ inline uint64_t M_sum_masked(const uint64_t *__restrict__ words,
     return s;
 }
 
+// The same for block offsets off < 2^31 in 32-bit arithmetic: the record's
+// byte offset is (off >> 5) * 16 = (off >> 1) & ~15, the mu sums within the
+// record are added in 32 bits and the records' M in 64, and an inactive
+// lane masks nothing in and adds no record.
+__device__ inline uint64_t M_sum_masked32(const uint64_t *__restrict__ words,
+                                          const uint32_t (&off)[K_UNROLL],
+                                          const bool (&act)[K_UNROLL])
+{
+    const char *base = reinterpret_cast<const char *>(words);
+    ulonglong2 rec[K_UNROLL];
+#pragma unroll
+    for (int u = 0; u < K_UNROLL; ++u)
+        rec[u] = *reinterpret_cast<const ulonglong2 *>(base + ((off[u] >> 1) & ~15u));
+    uint64_t s = 0;
+    int32_t d = 0;
+#pragma unroll
+    for (int u = 0; u < K_UNROLL; ++u) {
+        const uint32_t lm = act[u] ? (2u << (off[u] & 31)) - 1u : 0u;
+        d += __popc((uint32_t)rec[u].x & lm) - __popc((uint32_t)(rec[u].x >> 32) & lm);
+        s += act[u] ? rec[u].y : 0ull;
+    }
+    return s + (uint64_t)(int64_t)d;
+}
+
 // Explicit k part of one (tile, k-chunk) item with lanes as an 8 x 8 grid:
 // lane = 8 xi + kj takes x = 8 g + xi of x-group g and k = kk + kj, so one
 // gather instruction covers 8 neighbouring x and 8 neighbouring k, whose
@@ -1963,8 +2001,9 @@ __device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_
             const uint64_t ghi = uniform_u64(wave_max_u64(has ? hi : 0ull));
             uint64_t acc = 0;
             const double mf = (double)m;
+            const uint32_t y1lo = (uint32_t)b.y1;
             for (uint64_t kk = glo; kk <= ghi; kk += 8 * K_UNROLL) {
-                uint64_t off[K_UNROLL];
+                uint32_t off[K_UNROLL];
                 bool act[K_UNROLL];
 #pragma unroll
                 for (int u = 0; u < K_UNROLL; ++u) {
@@ -1974,12 +2013,13 @@ __device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_
                     const double t = trunc(qd);
                     // t is floor(m/k) when qd < 2^32 and not near an integer
                     const bool fast = qd < 4294967296.0 && fabs(qd - t - 0.5) <= 0.5 - QEPS;
-                    uint64_t y = (uint64_t)(uint32_t)t;
+                    uint32_t ylo = (uint32_t)t;
                     if (act[u] && !fast)
-                        y = fix_quotient_any(m, k, t);
-                    off[u] = act[u] ? y - b.y1 : 0ull;
+                        ylo = (uint32_t)fix_quotient_any(m, k, t);
+                    // y - y1 < 2^31: its low 32 bits are the difference of the low words
+                    off[u] = act[u] ? ylo - y1lo : 0u;
                 }
-                acc += M_sum_masked(b.words, off, act);
+                acc += M_sum_masked32(b.words, off, act);
             }
             acc += __shfl_xor(acc, 1, 64);
             acc += __shfl_xor(acc, 2, 64);
@@ -2216,6 +2256,43 @@ __device__ void finalize_keyed(const QueryArgs &q, uint32_t qi, uint64_t *red)
         }
         __syncthreads();
     }
+}
+
+// One level (lo, hi] of a keyed group's finalize across the whole grid (the
+// group of a dense window can hold 10^7 entries, far too many for one
+// workgroup): gsz lanes (a power of two up to 64, within one wave) share
+// one entry, its terms k strided over them.
+__global__ __launch_bounds__(256) void k_finalize_keyed_level(QueryArgs q, uint32_t qi, uint64_t lo,
+                                                             uint64_t hi, uint32_t gsz)
+{
+    const uint64_t L = q.q_L[qi], g0 = q.q_g0[qi], kb = q.q_koff[qi];
+    uint64_t *A = reinterpret_cast<uint64_t *>(q.A);
+    const uint64_t e0 = g0 + q.key_off[kb + lo], e1 = g0 + q.key_off[kb + hi];
+    const uint64_t gt = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t ei = gt / gsz;
+    const uint32_t sub = (uint32_t)(gt % gsz);
+    const bool active = ei < e1 - e0;
+    const uint64_t e = e0 + ei;
+    uint64_t s = 0;
+    if (active) {
+        const uint64_t x = q.key_x[e], m = q.x_m[e];
+        const uint64_t j = L / x;
+        for (uint64_t k = 2 + sub; k <= j; k += gsz)
+            s += A[key_find(q, g0, kb, k * x, m / k)];
+    }
+    for (uint32_t o = gsz / 2; o >= 1; o >>= 1)
+        s += __shfl_xor(s, (int)o, 64);
+    if (active && sub == 0)
+        A[e] = 1 - q.S[e] - s;
+}
+
+hipError_t launch_finalize_keyed_level(const QueryArgs &q, uint32_t qi, uint64_t lo, uint64_t hi,
+                                       uint64_t entries, uint32_t gsz, hipStream_t s)
+{
+    const uint64_t threads = entries * gsz;
+    hipLaunchKernelGGL(k_finalize_keyed_level, dim3((uint32_t)((threads + 255) / 256)), dim3(256),
+                       0, s, q, qi, lo, hi, gsz);
+    return hipGetLastError();
 }
 
 __global__ __launch_bounds__(FIN_THREADS) void k_finalize(QueryArgs q, const uint32_t *qlist)
