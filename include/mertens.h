@@ -207,9 +207,10 @@ int mertens_set_stream(void *hip_stream);
  *                 for testing, and disable keyed groups)
  *   "serve_capacity"  most requests in flight for mertens_submit (4096)
  *   "serve_x_budget"  most x entries of admitted requests (2^26 = 4 GiB)
- *   "serve_short_blocks" requests whose sweep ends within this many blocks
- *                 ride a separate short sweep, stepped alternately with the
- *                 main one (default 4)
+ *   "serve_short_blocks" S: requests are served in six lanes by the number
+ *                 of y-blocks their sweep needs (up to S, 4S, 16S, 64S, 256S,
+ *                 more), each lane its own cyclic sweep, one block of every
+ *                 busy lane per worker step (default 4)
  * Returns 0 or MERTENS_EINVAL (unknown key, value out of range, or a
  * non-serving key while the serving worker runs).
  */

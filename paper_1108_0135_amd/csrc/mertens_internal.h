@@ -177,6 +177,10 @@ hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, 
 // qlist = NULL finalizes queries 0..count-1, else the listed query indices
 hipError_t launch_finalize(const QueryArgs &q, const uint32_t *qlist, uint32_t count,
                            hipStream_t s);
+// level (lo, hi] of keyed group member qi's finalize (`entries` entries in
+// it), gsz lanes per entry (a power of two up to 64)
+hipError_t launch_finalize_keyed_level(const QueryArgs &q, uint32_t qi, uint64_t lo, uint64_t hi,
+                                       uint64_t entries, uint32_t gsz, hipStream_t s);
 hipError_t launch_collect(const QueryArgs &q, int64_t *out, hipStream_t s);
 // out[c-1] = A entry of (c, floor(n_qi/c)) for c = 1..count (keyed group member qi)
 hipError_t launch_keyed_byproducts(const QueryArgs &q, uint32_t qi, uint64_t count, int64_t *out,

@@ -538,6 +538,7 @@ struct Batch {
     std::vector<uint64_t> n, nhi, xb, L, g0, ymax, koff;
     uint32_t nwide = 0;
     std::vector<uint32_t> fin_list;  // plain queries and one member per keyed group
+    std::vector<uint32_t> key_off_h;  // host copy of key_off (keyed groups' levels)
     uint64_t X = 0, ymax_all = 0, keyed_entries = 0;
     uint32_t ntiles = 0;
     DevBuf q_n, q_L, q_g0, q_koff, x_m, x_Y, x_K, x_k0, S, A, x_klo, x_khi, key_x, key_off;
@@ -761,6 +762,7 @@ struct Batch {
         HIPCHK(hipMemcpyAsync(q_L.p, L.data(), nq * 8, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(q_g0.p, g0.data(), nq * 8, hipMemcpyHostToDevice, s));
         HIPCHK(hipMemcpyAsync(q_koff.p, koff.data(), nq * 8, hipMemcpyHostToDevice, s));
+        key_off_h = h_key_off;
         if (!h_key_off.empty())
             HIPCHK(hipMemcpyAsync(key_off.p, h_key_off.data(), h_key_off.size() * 4,
                                   hipMemcpyHostToDevice, s));
@@ -848,10 +850,32 @@ struct Batch {
     int finalize(const std::vector<uint32_t> &which, hipStream_t s)
     {
         if (which.empty()) {
-            HIPCHK(hipMemcpyAsync(qlist.p, fin_list.data(), fin_list.size() * 4,
-                                  hipMemcpyHostToDevice, s));
-            HIPCHK(launch_finalize(args, qlist.as<uint32_t>(), (uint32_t)fin_list.size(), s));
-            HIPCHK(hipStreamSynchronize(s));  // fin_list may change with the next plan
+            // keyed groups level by level across the whole grid, plain
+            // queries one workgroup each
+            std::vector<uint32_t> plain;
+            for (uint32_t qi : fin_list) {
+                if (koff[qi] == ~0ull) {
+                    plain.push_back(qi);
+                    continue;
+                }
+                const uint64_t Lq = L[qi], kbq = koff[qi];
+                for (uint64_t hi = Lq, lo = Lq / 2; hi >= 1; hi = lo, lo = lo / 2) {
+                    const uint64_t ne = (uint64_t)key_off_h[kbq + hi] - key_off_h[kbq + lo];
+                    if (ne == 0)
+                        continue;
+                    const uint64_t jmax = Lq / (lo + 1);  // terms of the level's smallest x
+                    uint32_t gsz = 1;
+                    while (gsz < 64 && (uint64_t)gsz * 16 < jmax)
+                        gsz *= 2;
+                    HIPCHK(launch_finalize_keyed_level(args, qi, lo, hi, ne, gsz, s));
+                }
+            }
+            if (!plain.empty()) {
+                HIPCHK(hipMemcpyAsync(qlist.p, plain.data(), plain.size() * 4,
+                                      hipMemcpyHostToDevice, s));
+                HIPCHK(launch_finalize(args, qlist.as<uint32_t>(), (uint32_t)plain.size(), s));
+            }
+            HIPCHK(hipStreamSynchronize(s));  // `plain` goes out of scope
         } else {
             HIPCHK(hipMemcpyAsync(qlist.p, which.data(), which.size() * 4, hipMemcpyHostToDevice,
                                   s));
@@ -910,11 +934,13 @@ struct Server {
     bool running = false, stop = false;
     int failure = 0;
     hipStream_t stream = nullptr;
-    // lane 0 sweeps the first serve_short_blocks blocks for requests that
-    // need no more; lane 1 sweeps for the rest.  Each worker step runs one
-    // block of each busy lane, so short requests never wait for the sweep
-    // of long ones.
-    ServeLane lanes[2];
+    // Lanes by the number of blocks a request needs: lane 0 up to
+    // serve_short_blocks (S), lane k up to S 4^k, the last one the rest.
+    // Each lane runs its own cyclic sweep over the blocks its requests
+    // need, and each worker step runs one block of each busy lane, so a
+    // request waits for the cycle of requests of about its own size only.
+    static constexpr int NLANES = 6;
+    ServeLane lanes[NLANES];
     std::deque<uint64_t> queued;
     std::map<uint64_t, ServeQuery> queries;
     uint64_t next_ticket = 1;
@@ -1262,6 +1288,18 @@ void serve_fail(int rc)
     v.queued.clear();
 }
 
+// The lane of a request (or batch) that needs `blocks` blocks.
+int serve_lane_of(uint64_t blocks)
+{
+    uint64_t lim = std::max<uint64_t>(g.serve_short_blocks, 1);
+    int k = 0;
+    while (k < Server::NLANES - 1 && blocks > lim) {
+        lim *= 4;
+        ++k;
+    }
+    return k;
+}
+
 // Plan the admitted tickets as one batch and put it on the lane its
 // longest request needs.
 int serve_admit(const std::vector<uint64_t> &tickets, uint64_t B)
@@ -1275,8 +1313,11 @@ int serve_admit(const std::vector<uint64_t> &tickets, uint64_t B)
         for (uint64_t t : tickets)
             ns.push_back(v.queries[t].n);
     }
-    for (uint64_t x : ns)
-        us.push_back(g.u_req ? g.u_req : auto_u((long double)x, g.tune.u_scale));
+    // the requests admitted together share one split u, as one query call
+    // does (u ~ (sum of their n)^(2/3)): the update work, ~ (sum of n) /
+    // sqrt(u), then falls, the sweep grows by much less
+    const uint64_t u_shared = g.u_req ? g.u_req : auto_u(effective_total_n(ns), g.tune.u_scale);
+    us.assign(ns.size(), u_shared);
     // no keyed groups here: requests complete and finalize one by one
     RCCHK(sb->b.plan(ns, us, g.tune, s, false));
     sb->tickets = tickets;
@@ -1285,6 +1326,13 @@ int serve_admit(const std::vector<uint64_t> &tickets, uint64_t B)
     uint64_t maxlb = 0;
     {
         std::lock_guard<std::mutex> lk(v.mu);
+        // admission reserved each request's entries at its own u; the batch
+        // holds b.X entries at the shared u (never more)
+        uint64_t reserved = 0;
+        for (uint64_t x : ns)
+            reserved += std::max<uint64_t>(1, x / (g.u_req ? g.u_req : auto_u((long double)x,
+                                                                              g.tune.u_scale)));
+        v.x_used = v.x_used - std::min(v.x_used, reserved) + sb->b.X;
         for (size_t i = 0; i < tickets.size(); ++i) {
             ServeQuery &q = v.queries[tickets[i]];
             q.state = 1;
@@ -1295,7 +1343,7 @@ int serve_admit(const std::vector<uint64_t> &tickets, uint64_t B)
             maxlb = std::max(maxlb, q.last_block);
         }
     }
-    v.lanes[maxlb < g.serve_short_blocks ? 0 : 1].batches.push_back(std::move(sb));
+    v.lanes[serve_lane_of(maxlb + 1)].batches.push_back(std::move(sb));
     return 0;
 }
 
@@ -1397,7 +1445,7 @@ int serve_step(std::vector<uint64_t> &admit)
     Server &v = g.srv;
     const uint64_t B = g.block_req ? g.block_req : (1ull << 30);
     if (!admit.empty()) {
-        std::vector<uint64_t> by_lane[2];
+        std::vector<uint64_t> by_lane[Server::NLANES];
         for (uint64_t t : admit) {
             uint64_t n;
             {
@@ -1406,7 +1454,7 @@ int serve_step(std::vector<uint64_t> &admit)
             }
             const uint64_t u = g.u_req ? g.u_req : auto_u((long double)n, g.tune.u_scale);
             const uint64_t L = std::max<uint64_t>(1, n / u);
-            by_lane[(n / (L + 1)) / B < g.serve_short_blocks ? 0 : 1].push_back(t);
+            by_lane[serve_lane_of((n / (L + 1)) / B + 1)].push_back(t);
         }
         for (auto &tl : by_lane) {
             if (tl.empty())
@@ -1445,8 +1493,10 @@ void serve_loop()
         {
             std::unique_lock<std::mutex> lk(v.mu);
             v.cv.wait(lk, [&] {
-                return v.stop || !v.queued.empty() || !v.lanes[0].batches.empty() ||
-                       !v.lanes[1].batches.empty();
+                bool busy = false;
+                for (const ServeLane &ln : v.lanes)
+                    busy = busy || !ln.batches.empty();
+                return v.stop || !v.queued.empty() || busy;
             });
             if (v.stop)
                 break;
