@@ -1965,6 +1965,114 @@ __device__ inline uint64_t M_sum_masked32(const uint64_t *__restrict__ words,
 // 8 k-lanes and leave with one 64-lane atomic per item.
 constexpr uint32_t K2D_SUB = 512;  // k per reciprocal sub-chunk (4 KB of LDS)
 
+// 1/k raised by four units in the last place (rcp_1ulp, then +4 in the
+// bits): for m < 2^48 the product m * rcp_up(k) rounded once lies in
+// [m/k, (m/k)(1 + 2^-49.5)], whose floor is floor(m/k) (see rl_pass).
+__device__ inline double rcp_up(double k)
+{
+    return __longlong_as_double(__double_as_longlong(rcp_1ulp(k)) + 4);
+}
+
+constexpr int K2F_UNROLL = 8;  // record loads in flight per lane
+// A y offset that no lane of a block can have: its record byte offset
+// (0x7FFFFFF0) lies past every block's records, where a buffer load reads
+// zeros (empty masks, M = 0), and its shift below is 0.
+constexpr uint32_t OFF_NONE = ~0u;
+
+// The 8 x 8 walk of k_item_2d for tiles whose m are all below 2^48, with no
+// branch per pair.
+// * y - y1 = trunc(fma(m, rcp_up(k), -y1)).  In a block from y1 = 0 this is
+//   the product above.  From y1 > 0 with y2 - y1 < y1: active pairs have
+//   k <= m/y1, so the product's excess over floor(m/k) stays below the next
+//   integer by more than (1/k)(1 - m 2^-49.6) >= 0.67 y1/m, while the one
+//   rounding of the fused result (< 2^31 = y2 - y1 + 1 <= y1) moves it by at
+//   most (y2 - y1 + 1) 2^-53 < 0.67 y1 / m; rounding never goes below the
+//   integer floor(m/k) - y1 either, since the exact value exceeds it.
+// * Records come through buffer loads whose range is the block's records;
+//   lanes outside their x's k range take OFF_NONE and add nothing.
+// * The mu sum up to y within its record is the population count of each
+//   mask shifted left by 31 - (y mod 32) (the low five bits of ~off).
+__device__ inline void k_item_2d_fast(const QueryArgs &q, const BlockArgs &b, uint32_t tile,
+                                      uint64_t kb, uint64_t ke, double *rk)
+{
+    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
+    const uint32_t lane = lane_id(), xi = lane >> 3, kj = lane & 7u;
+    const uint32_t nx = __builtin_amdgcn_readfirstlane(q.tile_nx[tile]);
+    const uint64_t g0 = uniform_u64(q.tile_g0[tile]);
+    const uint32_t rec_bytes = ((uint32_t)((b.y2 - b.y1) >> 5) + 1u) * 16u;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(b.words, (short)0, (int)rec_bytes, 0x00020000);
+    const double ny1 = -(double)b.y1;
+    uint64_t mine = 0;  // lane holds x = 8 kj + xi
+    for (uint64_t sb = kb; sb <= ke; sb += K2D_SUB) {
+        const uint64_t se = (ke - sb) < K2D_SUB - 1 ? ke : sb + K2D_SUB - 1;
+        const uint32_t ns = (uint32_t)(se - sb) + 1;
+        // the previous sub-chunk's readers are done with rk
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        for (uint32_t i = lane; i < ns; i += 64)
+            rk[i] = rcp_up((double)(sb + i));
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll 1
+        for (uint32_t g = 0; g < 8; ++g) {
+            const uint32_t xl = 8 * g + xi;
+            uint64_t m = 0, lo = 1, hi = 0;
+            if (xl < nx) {
+                m = q.x_m[g0 + xl];
+                lo = q.x_klo[g0 + xl];
+                hi = q.x_khi[g0 + xl];
+                lo = lo > sb ? lo : sb;
+                hi = hi < se ? hi : se;
+            }
+            const bool has = lo <= hi;
+            const uint64_t glo = uniform_u64(wave_min_u64(has ? lo : ~0ull));
+            const uint64_t ghi = uniform_u64(wave_max_u64(has ? hi : 0ull));
+            // pair k = sb + i is active when (i - lo_r) mod 2^32 < cnt
+            const uint32_t lo_r = (uint32_t)(lo - sb);
+            const uint32_t cnt = has ? (uint32_t)(hi - lo) + 1u : 0u;
+            const double mf = (double)m;
+            uint64_t ms = 0;
+            uint32_t dp = 0, dn = 0;
+            if (glo <= ghi) {
+                // indices read reach (ghi - sb) + 63 < ns + 63 < 3 K2D_SUB / 2:
+                // inside the wave's LDS slice; values past ns are never used
+                const uint32_t ilo = (uint32_t)(glo - sb), ihi = (uint32_t)(ghi - sb);
+                for (uint32_t kr = ilo; kr <= ihi; kr += 8 * K2F_UNROLL) {
+                    const uint32_t i0 = kr + kj;
+                    const uint32_t d0 = i0 - lo_r;
+                    uint32_t off[K2F_UNROLL];
+#pragma unroll
+                    for (int u = 0; u < K2F_UNROLL; ++u) {
+                        const uint32_t o = (uint32_t)fma(mf, rk[i0 + 8 * u], ny1);
+                        off[u] = d0 + 8u * u < cnt ? o : OFF_NONE;
+                    }
+                    v4u rec[K2F_UNROLL];
+#pragma unroll
+                    for (int u = 0; u < K2F_UNROLL; ++u)
+                        rec[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (off[u] >> 1) & ~15u, 0, 0);
+#pragma unroll
+                    for (int u = 0; u < K2F_UNROLL; ++u) {
+                        const uint32_t sh = ~off[u] & 31u;
+                        dp += (uint32_t)__popc(rec[u].x << sh);
+                        dn += (uint32_t)__popc(rec[u].y << sh);
+                        ms += (uint64_t)rec[u].z | ((uint64_t)rec[u].w << 32);
+                    }
+                }
+            }
+            uint64_t acc = ms + (uint64_t)(int64_t)(int32_t)(dp - dn);
+            acc += __shfl_xor(acc, 1, 64);
+            acc += __shfl_xor(acc, 2, 64);
+            acc += __shfl_xor(acc, 4, 64);
+            if (kj == g)
+                mine += acc;
+        }
+    }
+    const uint32_t xo = 8 * kj + xi;
+    if (xo < nx)
+        atomicAdd((unsigned long long *)&q.S[g0 + xo], (unsigned long long)mine);
+}
+
 __device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_t tile,
                                  uint64_t c, double *rk)
 {
@@ -1974,6 +2082,13 @@ __device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_
     const uint64_t kb = uniform_u64(q.tile_klo[tile]) + c * q.kchunk;
     const uint64_t tkhi = uniform_u64(q.tile_khi[tile]);
     const uint64_t ke = (tkhi - kb) < (uint64_t)q.kchunk - 1 ? tkhi : kb + q.kchunk - 1;
+    if (q.rl_fast && (b.y1 == 0 || b.y2 - b.y1 < b.y1)) {
+        const uint64_t mmax = uniform_u64(wave_max_u64(lane < nx ? q.x_m[g0 + lane] : 0ull));
+        if (mmax < (1ull << 48)) {
+            k_item_2d_fast(q, b, tile, kb, ke, rk);
+            return;
+        }
+    }
     uint64_t mine = 0;  // lane holds x = 8 kj + xi
     for (uint64_t sb = kb; sb <= ke; sb += K2D_SUB) {
         const uint64_t se = (ke - sb) < K2D_SUB - 1 ? ke : sb + K2D_SUB - 1;
@@ -2123,6 +2238,7 @@ __global__ __launch_bounds__(UPD_THREADS, 3) void k_update(QueryArgs q, BlockArg
 {
     // per wave: compacted run-length entries or explicit-k reciprocals
     static_assert(RL_ENT_CAP * 2 >= K2D_SUB * 8, "LDS slice too small");
+    static_assert(RL_ENT_CAP / 4 >= K2D_SUB + 8 * K2F_UNROLL, "fast walk reads past the slice");
     __shared__ double wave_lds[UPD_THREADS / 64][RL_ENT_CAP / 4];
     const BlockArgs b = load_block(b_in);
     const uint32_t lane = lane_id();

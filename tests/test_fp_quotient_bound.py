@@ -10,6 +10,8 @@ CPU as on the GPU, so numpy reproduces the rule's values bit for bit.  It
 must hold on random pairs and on the adversarial ones: exact multiples
 (m = k y), m = k y - 1 just below them, and the largest m allowed.
 """
+from fractions import Fraction
+
 import numpy as np
 
 
@@ -51,3 +53,67 @@ def test_largest_m_small_y():
     for y0 in (1, 2, 3, 7, 65536, 2**31 - 1):
         y = np.full(m.size, y0, dtype=np.uint64)
         assert _all_errors(m, y)
+
+
+# The explicit-k walk folds the block start y1 into one fused multiply-add:
+# y - y1 = trunc(RN(m * r' - y1)), with one rounding of the exact value.  It
+# is taken for m < 2^48 in a block [y1, y2] with y1 = 0 or y2 - y1 < y1, for
+# k with floor(m/k) in the block.  The exact value is formed here in rational
+# arithmetic and rounded once (Python's int / int division rounds correctly).
+
+def _fused_off(m, k, y1, err_units):
+    r = 1.0 / float(k)
+    ru = (np.array([r]).view(np.int64) + 4 + err_units).view(np.float64)[0]
+    num, den = Fraction(ru).as_integer_ratio()
+    v = (m * num - y1 * den) / den  # correctly rounded
+    return int(v)
+
+
+def _check_block(rng, y1, B, count):
+    y2 = y1 + B - 1
+    bad = []
+    for _ in range(count):
+        q = int(rng.integers(y1, y2 + 1))
+        if q == 0:
+            q = 1
+        kmax = (2**48 - 1) // (q + 1)
+        if kmax < 1:
+            continue
+        k = int(rng.integers(max(1, kmax - 1000), kmax + 1)) if rng.random() < 0.5 \
+            else int(rng.integers(1, kmax + 1))
+        # largest fraction (m = q k + k - 1), exact multiple, and in between
+        for m in (q * k + k - 1, q * k, q * k + int(rng.integers(0, k))):
+            if m >= 2**48 or not (y1 <= m // k <= y2):
+                continue
+            for e in (-1, 0, 1):
+                if _fused_off(m, k, y1, e) != m // k - y1:
+                    bad.append((m, k, y1, e))
+    return bad
+
+
+def test_fused_block_offset():
+    rng = np.random.default_rng(13)
+    bad = []
+    for B in (2**17, 2**24, 2**30, 2**31):
+        for b in (0, 1, 2, 3, 7, 1000, 2**20):
+            y1 = b * B
+            if y1 + B > 2**48:
+                continue
+            bad += _check_block(rng, y1, B, 600)
+    assert not bad, bad[:5]
+
+
+def test_fused_block_offset_top_of_block():
+    # quotients at the top of the block (the largest fused result) with the
+    # largest k that reaches them
+    bad = []
+    for B in (2**30, 2**31):
+        for b in (1, 2, 5, 100):
+            y1 = b * B
+            for q in (y1 + B - 1, y1 + B - 2, y1 + B // 2):
+                k = (2**48 - 1) // (q + 1)
+                for m in (q * k + k - 1, q * k):
+                    for e in (-1, 0, 1):
+                        if _fused_off(m, k, y1, e) != m // k - y1:
+                            bad.append((m, k, y1, e))
+    assert not bad, bad[:5]
