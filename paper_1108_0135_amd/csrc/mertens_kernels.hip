@@ -1596,7 +1596,16 @@ __device__ inline double rcp_1ulp(double y)
 //   running max of |qh - t| detects; such entries redo the RL_XS pairs with
 //   the integer fix-up.  With YCHECK, pairs with y > Y_x are skipped
 //   (sub-chunks that straddle some x's Y); *cnt counts the pairs taken.
-enum { RL_FAST = 0, RL_NEAR = 1, RL_NEAR_Y = 2 };
+// * FAST23 (as FAST, and every quotient of the pass below 2^23): with the
+//   same r', fma(m, r', 2^52 - 1/2) is exactly 2^52 + floor(m/y), since the
+//   exact m r' + 2^52 - 1/2 lies strictly between 2^52 + q - 1/2 and
+//   2^52 + q + 1/2 and one rounding takes it to the integer grid of
+//   [2^52, 2^53); the low word of the result is q, added with its sign by a
+//   24-bit multiply-add into 32-bit sums (at most 48 entries per lane and
+//   pass, |sum| < 2^29): two ops per pair.
+enum { RL_FAST = 0, RL_NEAR = 1, RL_NEAR_Y = 2, RL_FAST23 = 3 };
+constexpr double RL_MAGIC = 4503599627370495.5;  // 2^52 - 1/2
+constexpr double RL_Q23 = 8388608.0;             // 2^23
 
 template <int MODE>
 __device__ inline void rl_pass(const uint16_t *ent, uint32_t total, uint32_t wb0,
@@ -1605,6 +1614,10 @@ __device__ inline void rl_pass(const uint16_t *ent, uint32_t total, uint32_t wb0
 {
     constexpr bool YCHECK = MODE == RL_NEAR_Y;
     const uint32_t lane = lane_id();
+    int acc32[RL_XS];
+#pragma unroll
+    for (int i = 0; i < RL_XS; ++i)
+        acc32[i] = 0;
     for (uint32_t t = lane; t < total; t += 64) {
         const uint32_t e = ent[t];
         const uint32_t y = wb0 + (e & 0x0FFFu);
@@ -1614,6 +1627,20 @@ __device__ inline void rl_pass(const uint16_t *ent, uint32_t total, uint32_t wb0
 #pragma unroll
             for (int i = 0; i < RL_XS; ++i)
                 acc[i] = fma(sg, floor(mf[i] * ru), acc[i]);
+            continue;
+        }
+        if (MODE == RL_FAST23) {
+            const double ru = __longlong_as_double(__double_as_longlong(rcp_1ulp((double)y)) + 4);
+            int si = (e & 0x8000u) ? -1 : 1;
+            // opaque: a known +-1 factor is otherwise expanded into a
+            // conditional negation (four ops instead of one multiply-add)
+            __asm__ volatile("" : "+v"(si));
+#pragma unroll
+            for (int i = 0; i < RL_XS; ++i) {
+                // NaN m (past the tile) gives the canonical NaN: low word 0
+                const double t = fma(mf[i], ru, RL_MAGIC);
+                acc32[i] += __mul24((int)(uint32_t)__double_as_longlong(t), si);
+            }
             continue;
         }
         const double r = 1.0 / (double)y;
@@ -1645,6 +1672,11 @@ __device__ inline void rl_pass(const uint16_t *ent, uint32_t total, uint32_t wb0
                 }
             }
         }
+    }
+    if (MODE == RL_FAST23) {
+#pragma unroll
+        for (int i = 0; i < RL_XS; ++i)
+            acc[i] = (double)acc32[i];
     }
 }
 
@@ -1751,7 +1783,9 @@ __device__ inline void mu_item_lanes(const QueryArgs &q, const BlockArgs &b, uin
                 rl_pass<RL_NEAR_Y>(ent, total, (uint32_t)sb, mf, Yv, xm, acc, &c);
                 nq += c;
             } else {
-                if (q.rl_fast && (double)mmax < RL_M_EXACT)
+                if (q.rl_fast && (double)mmax < RL_M_EXACT && (double)mmax < RL_Q23 * (double)ss)
+                    rl_pass<RL_FAST23>(ent, total, (uint32_t)sb, mf, Yv, xm, acc, nullptr);
+                else if (q.rl_fast && (double)mmax < RL_M_EXACT)
                     rl_pass<RL_FAST>(ent, total, (uint32_t)sb, mf, Yv, xm, acc, nullptr);
                 else
                     rl_pass<RL_NEAR>(ent, total, (uint32_t)sb, mf, Yv, xm, acc, nullptr);
@@ -1973,14 +2007,53 @@ __device__ inline double rcp_up(double k)
     return __longlong_as_double(__double_as_longlong(rcp_1ulp(k)) + 4);
 }
 
-constexpr int K2F_UNROLL = 8;  // record loads in flight per lane
+// Record loads in flight per lane and batch of the walk below (8 x 8
+// lanes, 16 batches: 128 consecutive k per x in flight).  Measured at
+// M(10^16): 16 beats 8 by 2%; issuing the next batch before summing the
+// current one (two alternating batches) was slower (registers spilled).
+constexpr int K2F_UNROLL = 16;
 // A y offset that no lane of a block can have: its record byte offset
 // (0x7FFFFFF0) lies past every block's records, where a buffer load reads
 // zeros (empty masks, M = 0), and its shift below is 0.
 constexpr uint32_t OFF_NONE = ~0u;
 
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// One batch of the walk: K2F_UNROLL pairs per lane, k = sb + i0 + 8u.
+struct K2Batch {
+    uint32_t off[K2F_UNROLL];
+    u32x4 rec[K2F_UNROLL];
+};
+
+__device__ inline void k2_issue(K2Batch &t, const __amdgpu_buffer_rsrc_t rs, const double *rk,
+                                uint32_t i0, uint32_t lo_r, uint32_t cnt, double mf, double ny1)
+{
+    const uint32_t d0 = i0 - lo_r;
+#pragma unroll
+    for (int u = 0; u < K2F_UNROLL; ++u) {
+        const uint32_t o = (uint32_t)fma(mf, rk[i0 + 8 * u], ny1);
+        t.off[u] = d0 + 8u * u < cnt ? o : OFF_NONE;
+    }
+#pragma unroll
+    for (int u = 0; u < K2F_UNROLL; ++u)
+        t.rec[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (t.off[u] >> 1) & ~15u, 0, 0);
+}
+
+__device__ inline void k2_consume(const K2Batch &t, uint32_t &dp, uint32_t &dn, uint64_t &ms)
+{
+#pragma unroll
+    for (int u = 0; u < K2F_UNROLL; ++u) {
+        const uint32_t sh = ~t.off[u] & 31u;
+        dp += (uint32_t)__popc(t.rec[u].x << sh);
+        dn += (uint32_t)__popc(t.rec[u].y << sh);
+        ms += (uint64_t)t.rec[u].z | ((uint64_t)t.rec[u].w << 32);
+    }
+}
+
 // The 8 x 8 walk of k_item_2d for tiles whose m are all below 2^48, with no
-// branch per pair.
+// branch per pair.  Lane l brings m, k_lo and k_hi of the tile's x l (taken
+// once per item; lanes past the tile hold an empty range), and each group of
+// eight x reads them by lane exchange.
 // * y - y1 = trunc(fma(m, rcp_up(k), -y1)).  In a block from y1 = 0 this is
 //   the product above.  From y1 > 0 with y2 - y1 < y1: active pairs have
 //   k <= m/y1, so the product's excess over floor(m/k) stays below the next
@@ -1993,9 +2066,9 @@ constexpr uint32_t OFF_NONE = ~0u;
 // * The mu sum up to y within its record is the population count of each
 //   mask shifted left by 31 - (y mod 32) (the low five bits of ~off).
 __device__ inline void k_item_2d_fast(const QueryArgs &q, const BlockArgs &b, uint32_t tile,
-                                      uint64_t kb, uint64_t ke, double *rk)
+                                      uint64_t kb, uint64_t ke, double *rk, uint64_t m_l,
+                                      uint64_t klo_l, uint64_t khi_l)
 {
-    typedef uint32_t v4u __attribute__((ext_vector_type(4)));
     const uint32_t lane = lane_id(), xi = lane >> 3, kj = lane & 7u;
     const uint32_t nx = __builtin_amdgcn_readfirstlane(q.tile_nx[tile]);
     const uint64_t g0 = uniform_u64(q.tile_g0[tile]);
@@ -2003,6 +2076,7 @@ __device__ inline void k_item_2d_fast(const QueryArgs &q, const BlockArgs &b, ui
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(b.words, (short)0, (int)rec_bytes, 0x00020000);
     const double ny1 = -(double)b.y1;
+    constexpr uint32_t STEP = 8 * K2F_UNROLL;
     uint64_t mine = 0;  // lane holds x = 8 kj + xi
     for (uint64_t sb = kb; sb <= ke; sb += K2D_SUB) {
         const uint64_t se = (ke - sb) < K2D_SUB - 1 ? ke : sb + K2D_SUB - 1;
@@ -2016,15 +2090,12 @@ __device__ inline void k_item_2d_fast(const QueryArgs &q, const BlockArgs &b, ui
         __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
         for (uint32_t g = 0; g < 8; ++g) {
-            const uint32_t xl = 8 * g + xi;
-            uint64_t m = 0, lo = 1, hi = 0;
-            if (xl < nx) {
-                m = q.x_m[g0 + xl];
-                lo = q.x_klo[g0 + xl];
-                hi = q.x_khi[g0 + xl];
-                lo = lo > sb ? lo : sb;
-                hi = hi < se ? hi : se;
-            }
+            const int src = (int)(8 * g + xi);
+            const uint64_t m = __shfl(m_l, src, 64);
+            uint64_t lo = __shfl(klo_l, src, 64);
+            uint64_t hi = __shfl(khi_l, src, 64);
+            lo = lo > sb ? lo : sb;
+            hi = hi < se ? hi : se;
             const bool has = lo <= hi;
             const uint64_t glo = uniform_u64(wave_min_u64(has ? lo : ~0ull));
             const uint64_t ghi = uniform_u64(wave_max_u64(has ? hi : 0ull));
@@ -2035,29 +2106,13 @@ __device__ inline void k_item_2d_fast(const QueryArgs &q, const BlockArgs &b, ui
             uint64_t ms = 0;
             uint32_t dp = 0, dn = 0;
             if (glo <= ghi) {
-                // indices read reach (ghi - sb) + 63 < ns + 63 < 3 K2D_SUB / 2:
+                // indices read reach (ghi - sb) + STEP - 1 < ns + STEP <= 3 K2D_SUB / 2:
                 // inside the wave's LDS slice; values past ns are never used
                 const uint32_t ilo = (uint32_t)(glo - sb), ihi = (uint32_t)(ghi - sb);
-                for (uint32_t kr = ilo; kr <= ihi; kr += 8 * K2F_UNROLL) {
-                    const uint32_t i0 = kr + kj;
-                    const uint32_t d0 = i0 - lo_r;
-                    uint32_t off[K2F_UNROLL];
-#pragma unroll
-                    for (int u = 0; u < K2F_UNROLL; ++u) {
-                        const uint32_t o = (uint32_t)fma(mf, rk[i0 + 8 * u], ny1);
-                        off[u] = d0 + 8u * u < cnt ? o : OFF_NONE;
-                    }
-                    v4u rec[K2F_UNROLL];
-#pragma unroll
-                    for (int u = 0; u < K2F_UNROLL; ++u)
-                        rec[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (off[u] >> 1) & ~15u, 0, 0);
-#pragma unroll
-                    for (int u = 0; u < K2F_UNROLL; ++u) {
-                        const uint32_t sh = ~off[u] & 31u;
-                        dp += (uint32_t)__popc(rec[u].x << sh);
-                        dn += (uint32_t)__popc(rec[u].y << sh);
-                        ms += (uint64_t)rec[u].z | ((uint64_t)rec[u].w << 32);
-                    }
+                for (uint32_t kr = ilo; kr <= ihi; kr += STEP) {
+                    K2Batch t;
+                    k2_issue(t, rs, rk, kr + kj, lo_r, cnt, mf, ny1);
+                    k2_consume(t, dp, dn, ms);
                 }
             }
             uint64_t acc = ms + (uint64_t)(int64_t)(int32_t)(dp - dn);
@@ -2083,9 +2138,15 @@ __device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_
     const uint64_t tkhi = uniform_u64(q.tile_khi[tile]);
     const uint64_t ke = (tkhi - kb) < (uint64_t)q.kchunk - 1 ? tkhi : kb + q.kchunk - 1;
     if (q.rl_fast && (b.y1 == 0 || b.y2 - b.y1 < b.y1)) {
-        const uint64_t mmax = uniform_u64(wave_max_u64(lane < nx ? q.x_m[g0 + lane] : 0ull));
-        if (mmax < (1ull << 48)) {
-            k_item_2d_fast(q, b, tile, kb, ke, rk);
+        // lane l: the tile's x l (an empty k range past the tile)
+        uint64_t m_l = 0, klo_l = 1, khi_l = 0;
+        if (lane < nx) {
+            m_l = q.x_m[g0 + lane];
+            klo_l = q.x_klo[g0 + lane];
+            khi_l = q.x_khi[g0 + lane];
+        }
+        if (uniform_u64(wave_max_u64(m_l)) < (1ull << 48)) {
+            k_item_2d_fast(q, b, tile, kb, ke, rk, m_l, klo_l, khi_l);
             return;
         }
     }

@@ -117,3 +117,39 @@ def test_fused_block_offset_top_of_block():
                         if _fused_off(m, k, y1, e) != m // k - y1:
                             bad.append((m, k, y1, e))
     assert not bad, bad[:5]
+
+
+# Run-length pairs whose quotients are all below 2^23 take the quotient as
+# the low word of fma(m, r', 2^52 - 1/2): the exact value m r' + 2^52 - 1/2
+# lies strictly between 2^52 + q - 1/2 and 2^52 + q + 1/2 (q = floor(m/y)),
+# so its one rounding to the integer grid of [2^52, 2^53) is 2^52 + q.
+
+MAGIC = 2.0**52 - 0.5
+
+
+def _magic_quot(m, y, err_units):
+    r = 1.0 / float(y)
+    ru = (np.array([r]).view(np.int64) + 4 + err_units).view(np.float64)[0]
+    assert Fraction(MAGIC) == Fraction(2**53 - 1, 2)  # exactly representable
+    num, den = Fraction(ru).as_integer_ratio()
+    v = (2 * m * num + (2**53 - 1) * den) / (2 * den)  # correctly rounded
+    bits = int(np.array([v]).view(np.int64)[0])
+    return bits - int(np.array([2.0**52]).view(np.int64)[0])
+
+
+def test_magic_low_word():
+    rng = np.random.default_rng(14)
+    bad = []
+    for _ in range(4000):
+        m = int(rng.integers(1, 2**48))
+        ylo = max(1, m // (2**23 - 1) + 1)  # quotients below 2^23
+        if ylo >= 2**32:
+            continue
+        y = int(rng.integers(ylo, min(2**32, m + 1))) if ylo <= m else ylo
+        for mm in (m, (m // y) * y, (m // y) * y + y - 1):
+            if mm >= 2**48 or mm < y:
+                continue
+            for e in (-1, 0, 1):
+                if _magic_quot(mm, y, e) != mm // y:
+                    bad.append((mm, y, e))
+    assert not bad, bad[:5]
