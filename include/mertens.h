@@ -196,7 +196,15 @@ int mertens_set_stream(void *hip_stream);
  *                 lists their multiples in per-segment buckets first
  *                 (default 2^20; scanning them per segment is faster below)
  *   "rl_fast"     1 (default): run-length quotients with m < 2^48 take the
- *                 test-free rounded-up fp64 floor; 0: always the tested path
+ *                 test-free rounded-up fp64 floor, and explicit-k quotients
+ *                 of such x the test-free fused form; 0: always the tested
+ *                 path (and no band, below)
+ *   "band_lo", "band_hi"  explicit-k pairs whose M(y) read has y in
+ *                 [2^band_lo, 2^band_hi) are summed y-major: each window of
+ *                 2^17 y of the block's records is staged in LDS once and
+ *                 read there by every x with quotients in it (band_lo 0, or
+ *                 17..30; band_hi up to 31; default [2^20, 2^28)); band_lo = 0
+ *                 turns it off.  Applies with direct launches only.
  *   "progress"    k > 0: a query waits for every k-th block and prints
  *                 "mertens: block i of n updated" on stderr, and for each
  *                 update window of a block ("update_window") prints one line

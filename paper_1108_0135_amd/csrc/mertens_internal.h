@@ -51,6 +51,9 @@ constexpr uint32_t IV_WGS = 2048, IV_THREADS = 256;
 // First index of the prime table that is sieved (table starts at 5; the
 // pattern covers 5, 7, 11, 13, so sieving starts at 17 = index 4).
 constexpr uint32_t FIRST_SIEVED = 4;
+// Windows of the y-major explicit-k pass (k_ek_window): 2^EKW_SHIFT y, whose
+// 16-byte records fill 64 KiB of LDS.
+constexpr uint32_t EKW_SHIFT = 17;
 constexpr int TILE = 64;                     // x per tile = one wavefront
 // explicit-k pairs per balanced work item (tiles whose x have k ranges too
 // different for the 8 x 8 walk): 256 per lane
@@ -166,14 +169,25 @@ hipError_t launch_square_buckets(const BlockArgs &b, hipStream_t s);
 hipError_t launch_prime_buckets(const BlockArgs &b, hipStream_t s, hipEvent_t fill0 = nullptr,
                                 hipEvent_t fill1 = nullptr, hipEvent_t fill2 = nullptr);
 hipError_t launch_sieve(const BlockArgs &b, hipStream_t s);
-hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
+// per-block k ranges, -K M(Y) and item counts; with a band (wa < wb) the
+// explicit-k chunks of band tiles skip the gap the band leaves
+hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s,
+                              uint32_t wa = 0, uint32_t wb = 0);
 // wide entries: plan (once per sweep), per-block k ranges and -K*M(Y), and
 // the per-block run-length and explicit-k sums
 hipError_t launch_wide_plan(const QueryArgs &q, hipStream_t s);
 hipError_t launch_wide_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
 hipError_t launch_wide_update(const QueryArgs &q, const BlockArgs &b, hipStream_t s);
 hipError_t launch_scan_items(const QueryArgs &q, hipStream_t s);
-hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, hipStream_t s);
+// persistent update; explicit-k pairs with quotients in [2^wa, 2^wb) are
+// left to launch_ek_window when wa < wb (wa = wb = 0: none)
+hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, hipStream_t s,
+                         uint32_t wa = 0, uint32_t wb = 0);
+// those pairs within the block, y-major over windows of 2^17 y covering
+// [ystart, yend): ystart = max(2^wa, y1) a multiple of 2^17, yend =
+// min(2^wb, y2 + 1) <= 2^31
+hipError_t launch_ek_window(const QueryArgs &q, const BlockArgs &b, uint64_t ystart,
+                            uint64_t yend, hipStream_t s);
 // qlist = NULL finalizes queries 0..count-1, else the listed query indices
 hipError_t launch_finalize(const QueryArgs &q, const uint32_t *qlist, uint32_t count,
                            hipStream_t s);

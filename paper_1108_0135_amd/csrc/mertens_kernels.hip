@@ -1137,7 +1137,53 @@ constexpr int SCAN_THREADS = 1024;
 // Prep: per x, the k range whose quotients floor(m/k) land in [y1, y2]; the
 // one-off term -K*M(Y) when Y is in this block; per tile, the number of
 // work items of the run-length part and of the explicit k part.
-__global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockArgs b_in)
+// Explicit-k pairs whose quotient lies in the band [2^wa, 2^wb) of y
+// (wa < wb) are summed y-major by k_ek_window, for the tiles this predicate
+// selects (m below 2^48, the 8 x 8 walk, the fused quotient rule in the
+// block); the persistent update skips them.  For x with m, the band's k are
+// [floor(m / 2^wb) + 1, floor(m / 2^wa)].
+__device__ inline bool band_tile(const QueryArgs &q, const BlockArgs &b, uint64_t mmax,
+                                 uint32_t mode)
+{
+    return q.rl_fast && (b.y1 == 0 || b.y2 - b.y1 < b.y1) && mmax < (1ull << 48) && mode == 0;
+}
+
+// The k of a band tile left to the persistent update lie in [tmin, amax]
+// (below every x's band) and [bmin, tmax] (above it), from lane l's x (m,
+// its k range [klo, khi] in the block); amax = 0 when no x has k below its
+// band, bmin = ~0 when none above.  When amax + 1 >= bmin there is no gap.
+__device__ inline void band_gap(uint64_t m, uint64_t klo, uint64_t khi, uint32_t wa, uint32_t wb,
+                                uint64_t &amax, uint64_t &bmin)
+{
+    const bool has = klo <= khi;
+    const uint64_t hl = (m >> wb) + 1, hh = m >> wa;
+    const uint64_t ae = khi < hl - 1 ? khi : hl - 1;
+    const uint64_t bs = klo > hh + 1 ? klo : hh + 1;
+    amax = uniform_u64(wave_max_u64(has && klo <= ae ? ae : 0ull));
+    bmin = uniform_u64(wave_min_u64(has && bs <= khi ? bs : ~0ull));
+}
+
+// Work items of a mode-0 tile's explicit-k part: chunks of kchunk k over
+// [tmin, aend] (aend = amax when the band leaves a gap, else tmax), then
+// over [bmin, tmax] after a gap; n_a is the count of the first run.
+struct KChunks {
+    uint64_t aend, bmin, n_a, n_b;
+};
+
+__device__ inline KChunks k_chunks(uint64_t tmin, uint64_t tmax, uint32_t kchunk, bool gap,
+                                   uint64_t amax, uint64_t bmin)
+{
+    KChunks c;
+    const bool split = gap && amax + 1 < bmin;
+    c.aend = split ? amax : tmax;
+    c.bmin = bmin;
+    c.n_a = c.aend >= tmin ? (c.aend - tmin) / kchunk + 1 : 0;
+    c.n_b = split && bmin <= tmax ? (tmax - bmin) / kchunk + 1 : 0;
+    return c;
+}
+
+__global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockArgs b_in, uint32_t wa,
+                                                            uint32_t wb)
 {
     const BlockArgs b = load_block(b_in);
     const uint32_t tile =
@@ -1150,9 +1196,10 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockA
     const uint32_t nx = q.tile_nx[tile];
     const uint64_t g = q.tile_g0[tile] + lane;
     const uint64_t y1e = b.y1 > 0 ? b.y1 : 1;
-    uint64_t klo = 1, khi = 0;
+    uint64_t klo = 1, khi = 0, m = 0;
     if (lane < nx) {
-        const uint64_t m = q.x_m[g], K = q.x_K[g], k0 = q.x_k0[g], Y = q.x_Y[g];
+        m = q.x_m[g];
+        const uint64_t K = q.x_K[g], k0 = q.x_k0[g], Y = q.x_Y[g];
         uint64_t lo = m / (b.y2 + 1) + 1;
         if (lo < k0)
             lo = k0;
@@ -1186,19 +1233,23 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockA
     }
     const uint64_t slots =
         wave_sum_u64((lane & 7u) == 0 && glo <= ghi ? 8 * (ghi - glo + 1) : 0ull);
-    if (lane == 0) {
-        uint64_t nk = 0;
-        uint32_t mode = 0;
-        if (kpairs > 0) {
-            const uint64_t uni = tmax - tmin + 1;
-            if (q.kbal == 0 || q.kbal * kpairs >= slots) {
-                mode = 0;  // the 8 x 8 walk keeps at least 1/kbal of its lanes busy
-                nk = (uni + q.kchunk - 1) / q.kchunk;
-            } else {
-                mode = 1;  // balanced runs of the tile's pairs
-                nk = (kpairs + K_BAL_PAIRS - 1) / K_BAL_PAIRS;
-            }
+    uint64_t nk = 0;
+    uint32_t mode = 0;
+    if (kpairs > 0) {
+        if (q.kbal == 0 || q.kbal * kpairs >= slots) {
+            mode = 0;  // the 8 x 8 walk keeps at least 1/kbal of its lanes busy
+            uint64_t amax = 0, bmin = ~0ull;
+            const bool gap = wa < wb && band_tile(q, b, uniform_u64(wave_max_u64(m)), 0);
+            if (gap)
+                band_gap(m, klo, khi, wa, wb, amax, bmin);
+            const KChunks c = k_chunks(tmin, tmax, q.kchunk, gap, amax, bmin);
+            nk = c.n_a + c.n_b;
+        } else {
+            mode = 1;  // balanced runs of the tile's pairs
+            nk = (kpairs + K_BAL_PAIRS - 1) / K_BAL_PAIRS;
         }
+    }
+    if (lane == 0) {
         q.tile_klo[tile] = tmin;
         q.tile_khi[tile] = tmax;
         q.tile_mode[tile] = mode;
@@ -1483,10 +1534,11 @@ hipError_t launch_wide_update(const QueryArgs &q, const BlockArgs &b, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s)
+hipError_t launch_update_prep(const QueryArgs &q, const BlockArgs &b, hipStream_t s, uint32_t wa,
+                              uint32_t wb)
 {
     const uint32_t grid = (q.ntiles + 3) / 4;
-    hipLaunchKernelGGL(k_update_prep, dim3(grid), dim3(UPD_THREADS), 0, s, q, b);
+    hipLaunchKernelGGL(k_update_prep, dim3(grid), dim3(UPD_THREADS), 0, s, q, b, wa, wb);
     return hipGetLastError();
 }
 
@@ -2019,36 +2071,89 @@ constexpr uint32_t OFF_NONE = ~0u;
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-// One batch of the walk: K2F_UNROLL pairs per lane, k = sb + i0 + 8u.
-struct K2Batch {
-    uint32_t off[K2F_UNROLL];
-    u32x4 rec[K2F_UNROLL];
+// Record sources of the walk below, by y offset from the base the offsets
+// are taken from (OFF_NONE: the empty record).
+// Global: buffer loads whose range is the block's records (a load past it
+// reads zeros).
+struct RecGlobal {
+    __amdgpu_buffer_rsrc_t rs;
+    __device__ u32x4 operator()(uint32_t off) const
+    {
+        return __builtin_amdgcn_raw_buffer_load_b128(rs, (off >> 1) & ~15u, 0, 0);
+    }
+};
+// LDS: a window of nrec records followed by one empty record.
+struct RecLds {
+    const u32x4 *win;
+    uint32_t nrec;
+    __device__ u32x4 operator()(uint32_t off) const
+    {
+        const uint32_t r = off >> 5;
+        return win[r < nrec ? r : nrec];
+    }
 };
 
-__device__ inline void k2_issue(K2Batch &t, const __amdgpu_buffer_rsrc_t rs, const double *rk,
-                                uint32_t i0, uint32_t lo_r, uint32_t cnt, double mf, double ny1)
+// One batch of the walk: U pairs per lane, k = sb + i0 + 8u.
+template <int U>
+struct K2Batch {
+    uint32_t off[U];
+    u32x4 rec[U];
+};
+
+template <int U, class Src>
+__device__ inline void k2_issue(K2Batch<U> &t, const Src &src, const double *rk, uint32_t i0,
+                                uint32_t lo_r, uint32_t cnt, double mf, double ny1)
 {
     const uint32_t d0 = i0 - lo_r;
 #pragma unroll
-    for (int u = 0; u < K2F_UNROLL; ++u) {
+    for (int u = 0; u < U; ++u) {
         const uint32_t o = (uint32_t)fma(mf, rk[i0 + 8 * u], ny1);
         t.off[u] = d0 + 8u * u < cnt ? o : OFF_NONE;
     }
 #pragma unroll
-    for (int u = 0; u < K2F_UNROLL; ++u)
-        t.rec[u] = __builtin_amdgcn_raw_buffer_load_b128(rs, (t.off[u] >> 1) & ~15u, 0, 0);
+    for (int u = 0; u < U; ++u)
+        t.rec[u] = src(t.off[u]);
 }
 
-__device__ inline void k2_consume(const K2Batch &t, uint32_t &dp, uint32_t &dn, uint64_t &ms)
+template <int U>
+__device__ inline void k2_consume(const K2Batch<U> &t, uint32_t &dp, uint32_t &dn, uint64_t &ms)
 {
 #pragma unroll
-    for (int u = 0; u < K2F_UNROLL; ++u) {
+    for (int u = 0; u < U; ++u) {
         const uint32_t sh = ~t.off[u] & 31u;
         dp += (uint32_t)__popc(t.rec[u].x << sh);
         dn += (uint32_t)__popc(t.rec[u].y << sh);
         ms += (uint64_t)t.rec[u].z | ((uint64_t)t.rec[u].w << 32);
     }
 }
+
+// The pairs k in [lo, hi] (this lane's x; sb <= lo) of one group of eight x
+// over the reciprocal table rk of the sub-chunk from sb: the group walks the
+// union of its lanes' ranges, 8 x 8 lanes, batches of U pairs per lane.
+template <int U, class Src>
+__device__ inline void k2_walk(const Src &src, const double *rk, uint64_t sb, uint32_t kj,
+                               double mf, double ny1, uint64_t lo, uint64_t hi, uint32_t &dp,
+                               uint32_t &dn, uint64_t &ms)
+{
+    constexpr uint32_t STEP = 8 * U;
+    const bool has = lo <= hi;
+    const uint64_t glo = uniform_u64(wave_min_u64(has ? lo : ~0ull));
+    const uint64_t ghi = uniform_u64(wave_max_u64(has ? hi : 0ull));
+    if (glo > ghi)
+        return;
+    // pair k = sb + i is active when (i - lo_r) mod 2^32 < cnt
+    const uint32_t lo_r = (uint32_t)(lo - sb);
+    const uint32_t cnt = has ? (uint32_t)(hi - lo) + 1u : 0u;
+    // indices read reach (ghi - sb) + STEP - 1 < K2D_SUB + STEP: inside the
+    // table's slice; values past the filled ones are never used
+    const uint32_t ilo = (uint32_t)(glo - sb), ihi = (uint32_t)(ghi - sb);
+    for (uint32_t kr = ilo; kr <= ihi; kr += STEP) {
+        K2Batch<U> t;
+        k2_issue<U>(t, src, rk, kr + kj, lo_r, cnt, mf, ny1);
+        k2_consume<U>(t, dp, dn, ms);
+    }
+}
+
 
 // The 8 x 8 walk of k_item_2d for tiles whose m are all below 2^48, with no
 // branch per pair.  Lane l brings m, k_lo and k_hi of the tile's x l (taken
@@ -2065,18 +2170,20 @@ __device__ inline void k2_consume(const K2Batch &t, uint32_t &dp, uint32_t &dn, 
 //   lanes outside their x's k range take OFF_NONE and add nothing.
 // * The mu sum up to y within its record is the population count of each
 //   mask shifted left by 31 - (y mod 32) (the low five bits of ~off).
+// * With a band (wa < wb), each x's band k are left out (two walks, below
+//   and above them).
 __device__ inline void k_item_2d_fast(const QueryArgs &q, const BlockArgs &b, uint32_t tile,
                                       uint64_t kb, uint64_t ke, double *rk, uint64_t m_l,
-                                      uint64_t klo_l, uint64_t khi_l)
+                                      uint64_t klo_l, uint64_t khi_l, uint32_t wa, uint32_t wb)
 {
     const uint32_t lane = lane_id(), xi = lane >> 3, kj = lane & 7u;
     const uint32_t nx = __builtin_amdgcn_readfirstlane(q.tile_nx[tile]);
     const uint64_t g0 = uniform_u64(q.tile_g0[tile]);
     const uint32_t rec_bytes = ((uint32_t)((b.y2 - b.y1) >> 5) + 1u) * 16u;
-    const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(b.words, (short)0, (int)rec_bytes, 0x00020000);
+    const RecGlobal src{
+        __builtin_amdgcn_make_buffer_rsrc(b.words, (short)0, (int)rec_bytes, 0x00020000)};
     const double ny1 = -(double)b.y1;
-    constexpr uint32_t STEP = 8 * K2F_UNROLL;
+    const bool band = wa < wb;
     uint64_t mine = 0;  // lane holds x = 8 kj + xi
     for (uint64_t sb = kb; sb <= ke; sb += K2D_SUB) {
         const uint64_t se = (ke - sb) < K2D_SUB - 1 ? ke : sb + K2D_SUB - 1;
@@ -2090,30 +2197,23 @@ __device__ inline void k_item_2d_fast(const QueryArgs &q, const BlockArgs &b, ui
         __builtin_amdgcn_wave_barrier();
 #pragma unroll 1
         for (uint32_t g = 0; g < 8; ++g) {
-            const int src = (int)(8 * g + xi);
-            const uint64_t m = __shfl(m_l, src, 64);
-            uint64_t lo = __shfl(klo_l, src, 64);
-            uint64_t hi = __shfl(khi_l, src, 64);
+            const int sl = (int)(8 * g + xi);
+            const uint64_t m = __shfl(m_l, sl, 64);
+            uint64_t lo = __shfl(klo_l, sl, 64);
+            uint64_t hi = __shfl(khi_l, sl, 64);
             lo = lo > sb ? lo : sb;
             hi = hi < se ? hi : se;
-            const bool has = lo <= hi;
-            const uint64_t glo = uniform_u64(wave_min_u64(has ? lo : ~0ull));
-            const uint64_t ghi = uniform_u64(wave_max_u64(has ? hi : 0ull));
-            // pair k = sb + i is active when (i - lo_r) mod 2^32 < cnt
-            const uint32_t lo_r = (uint32_t)(lo - sb);
-            const uint32_t cnt = has ? (uint32_t)(hi - lo) + 1u : 0u;
             const double mf = (double)m;
             uint64_t ms = 0;
             uint32_t dp = 0, dn = 0;
-            if (glo <= ghi) {
-                // indices read reach (ghi - sb) + STEP - 1 < ns + STEP <= 3 K2D_SUB / 2:
-                // inside the wave's LDS slice; values past ns are never used
-                const uint32_t ilo = (uint32_t)(glo - sb), ihi = (uint32_t)(ghi - sb);
-                for (uint32_t kr = ilo; kr <= ihi; kr += STEP) {
-                    K2Batch t;
-                    k2_issue(t, rs, rk, kr + kj, lo_r, cnt, mf, ny1);
-                    k2_consume(t, dp, dn, ms);
-                }
+            if (band) {
+                const uint64_t hl = (m >> wb) + 1, hh = m >> wa;  // the band's k
+                k2_walk<K2F_UNROLL>(src, rk, sb, kj, mf, ny1, lo, hi < hl - 1 ? hi : hl - 1, dp,
+                                    dn, ms);
+                k2_walk<K2F_UNROLL>(src, rk, sb, kj, mf, ny1, lo > hh + 1 ? lo : hh + 1, hi, dp,
+                                    dn, ms);
+            } else {
+                k2_walk<K2F_UNROLL>(src, rk, sb, kj, mf, ny1, lo, hi, dp, dn, ms);
             }
             uint64_t acc = ms + (uint64_t)(int64_t)(int32_t)(dp - dn);
             acc += __shfl_xor(acc, 1, 64);
@@ -2129,14 +2229,15 @@ __device__ inline void k_item_2d_fast(const QueryArgs &q, const BlockArgs &b, ui
 }
 
 __device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_t tile,
-                                 uint64_t c, double *rk)
+                                 uint64_t c, double *rk, uint32_t wa, uint32_t wb)
 {
     const uint32_t lane = lane_id(), xi = lane >> 3, kj = lane & 7u;
     const uint32_t nx = __builtin_amdgcn_readfirstlane(q.tile_nx[tile]);
     const uint64_t g0 = uniform_u64(q.tile_g0[tile]);
-    const uint64_t kb = uniform_u64(q.tile_klo[tile]) + c * q.kchunk;
+    const uint64_t tklo = uniform_u64(q.tile_klo[tile]);
     const uint64_t tkhi = uniform_u64(q.tile_khi[tile]);
-    const uint64_t ke = (tkhi - kb) < (uint64_t)q.kchunk - 1 ? tkhi : kb + q.kchunk - 1;
+    uint64_t kb = tklo + c * q.kchunk;
+    uint64_t ke = (tkhi - kb) < (uint64_t)q.kchunk - 1 ? tkhi : kb + q.kchunk - 1;
     if (q.rl_fast && (b.y1 == 0 || b.y2 - b.y1 < b.y1)) {
         // lane l: the tile's x l (an empty k range past the tile)
         uint64_t m_l = 0, klo_l = 1, khi_l = 0;
@@ -2146,7 +2247,18 @@ __device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_
             khi_l = q.x_khi[g0 + lane];
         }
         if (uniform_u64(wave_max_u64(m_l)) < (1ull << 48)) {
-            k_item_2d_fast(q, b, tile, kb, ke, rk, m_l, klo_l, khi_l);
+            if (wa < wb) {  // a band tile: its chunks skip the gap the band leaves
+                uint64_t amax, bmin;
+                band_gap(m_l, klo_l, khi_l, wa, wb, amax, bmin);
+                const KChunks ch = k_chunks(tklo, tkhi, q.kchunk, true, amax, bmin);
+                if (c < ch.n_a) {
+                    ke = (ch.aend - kb) < (uint64_t)q.kchunk - 1 ? ch.aend : kb + q.kchunk - 1;
+                } else {
+                    kb = ch.bmin + (c - ch.n_a) * q.kchunk;
+                    ke = (tkhi - kb) < (uint64_t)q.kchunk - 1 ? tkhi : kb + q.kchunk - 1;
+                }
+            }
+            k_item_2d_fast(q, b, tile, kb, ke, rk, m_l, klo_l, khi_l, wa, wb);
             return;
         }
     }
@@ -2214,10 +2326,10 @@ __device__ inline void k_item_2d(const QueryArgs &q, const BlockArgs &b, uint32_
 // neighbouring x alike) use the 8 x 8 grid above over k-chunks; mode 1
 // tiles use balanced runs of their pairs.
 __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t tile, uint64_t c,
-                              double *rk)
+                              double *rk, uint32_t wa, uint32_t wb)
 {
     if (__builtin_amdgcn_readfirstlane(q.tile_mode[tile]) == 0) {
-        k_item_2d(q, b, tile, c, rk);
+        k_item_2d(q, b, tile, c, rk, wa, wb);
         return;
     }
     // Balanced runs: the tile's pairs are numbered through an exclusive
@@ -2295,7 +2407,8 @@ __device__ inline void k_item(const QueryArgs &q, const BlockArgs &b, uint32_t t
 // one per item).  Three workgroups per CU (12 waves, up to 168 VGPRs): the
 // run-length passes keep 16 x of quotient state per lane, which at four
 // workgroups (128 VGPRs) spilled to scratch.
-__global__ __launch_bounds__(UPD_THREADS, 3) void k_update(QueryArgs q, BlockArgs b_in)
+__global__ __launch_bounds__(UPD_THREADS, 3) void k_update(QueryArgs q, BlockArgs b_in, uint32_t wa,
+                                                           uint32_t wb)
 {
     // per wave: compacted run-length entries or explicit-k reciprocals
     static_assert(RL_ENT_CAP * 2 >= K2D_SUB * 8, "LDS slice too small");
@@ -2319,7 +2432,7 @@ __global__ __launch_bounds__(UPD_THREADS, 3) void k_update(QueryArgs q, BlockArg
         if (local < nmu)
             mu_item(q, b, tile, local, ent);
         else
-            k_item(q, b, tile, local - nmu, wl);
+            k_item(q, b, tile, local - nmu, wl, wa, wb);
         // One ticket per wave.  Every lane executes the atomic (lane 0 adds
         // 1, the others 0) so no divergent branch guards it, and readfirstlane
         // turns the ticket into a scalar: the exit test is a uniform branch,
@@ -2330,9 +2443,135 @@ __global__ __launch_bounds__(UPD_THREADS, 3) void k_update(QueryArgs q, BlockArg
     }
 }
 
-hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, hipStream_t s)
+hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, hipStream_t s,
+                         uint32_t wa, uint32_t wb)
 {
-    hipLaunchKernelGGL(k_update, dim3(grid), dim3(UPD_THREADS), 0, s, q, b);
+    hipLaunchKernelGGL(k_update, dim3(grid), dim3(UPD_THREADS), 0, s, q, b, wa, wb);
+    return hipGetLastError();
+}
+
+// Explicit-k pairs of the band [2^wa, 2^wb), y-major: one workgroup per
+// (window of EKW_Y y, group of EKW_TILES tiles), windows of one band in
+// order, the groups of one window consecutive (they share its records in
+// L2).  The window's records are staged in LDS with coalesced loads; each
+// wave takes one tile and, for its x, the k whose quotient lies in the
+// window, k in [floor(m / (Y0 + EKW_Y)) + 1, floor(m / Y0)] (within the
+// block's k range), walked 8 x 8 as in k_item_2d_fast with the records read
+// from LDS.  Offsets are taken from Y0 (the window is no longer than Y0,
+// so the fused quotient rule above holds with y1 = Y0).  Windows start at
+// ystart (a multiple of EKW_Y, at least EKW_Y) and cover [ystart, yend);
+// yend <= 2^31.
+constexpr uint32_t EKW_Y = 1u << EKW_SHIFT;
+constexpr uint32_t EKW_REC = EKW_Y / 32;  // 4096 records = 64 KiB
+constexpr int EKW_THREADS = 1024;
+constexpr uint32_t EKW_TILES = EKW_THREADS / 64;
+constexpr int EKW_UNROLL = 8;  // LDS reads per lane and batch
+
+// floor(a / d) for a < 2^32, 1 <= d < 2^32: an fp64 estimate (within one
+// of the quotient) and one integer correction.
+__device__ inline uint32_t div_small(uint32_t a, uint32_t d)
+{
+    uint32_t qv = (uint32_t)((double)a * rcp_1ulp((double)d));
+    const int64_t r = (int64_t)a - (int64_t)qv * (int64_t)d;
+    if (r < 0)
+        qv -= 1;
+    else if (r >= (int64_t)d)
+        qv += 1;
+    return qv;
+}
+
+__global__ __launch_bounds__(EKW_THREADS) void k_ek_window(QueryArgs q, BlockArgs b_in,
+                                                           uint64_t ystart, uint64_t yend,
+                                                           uint32_t ngroups)
+{
+    __shared__ u32x4 win[EKW_REC + 1];
+    __shared__ uint32_t busy;
+    const BlockArgs b = load_block(b_in);
+    const uint32_t w = blockIdx.x / ngroups, grp = blockIdx.x % ngroups;
+    const uint64_t Y0 = ystart + (uint64_t)w * EKW_Y;
+    if (Y0 < b.y1 || Y0 > b.y2 || Y0 >= yend)
+        return;
+    const uint32_t tid = threadIdx.x, lane = lane_id();
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (tid == 0)
+        busy = 0;
+    // this wave's tile and, per x, the k whose quotient lies in the window:
+    // floor(m / (a 2^17)) = floor(floor(m / 2^17) / a)
+    const uint32_t tile = grp * EKW_TILES + wave;
+    uint32_t nx = 0;
+    uint64_t g0 = 0, m_l = 0, lo_l = 1, hi_l = 0, kb = 1, ke = 0;
+    if (tile < q.ntiles) {
+        nx = __builtin_amdgcn_readfirstlane(q.tile_nx[tile]);
+        g0 = uniform_u64(q.tile_g0[tile]);
+        if (lane < nx) {
+            m_l = q.x_m[g0 + lane];
+            lo_l = q.x_klo[g0 + lane];
+            hi_l = q.x_khi[g0 + lane];
+        }
+        if (band_tile(q, b, uniform_u64(wave_max_u64(m_l)), q.tile_mode[tile])) {
+            const uint32_t mh = (uint32_t)(m_l >> EKW_SHIFT);  // < 2^31
+            const uint32_t a = (uint32_t)(Y0 >> EKW_SHIFT);     // < 2^14 (Y0 < 2^31)
+            const uint64_t kw_hi = div_small(mh, a), kw_lo = (uint64_t)div_small(mh, a + 1) + 1;
+            lo_l = lo_l > kw_lo ? lo_l : kw_lo;
+            hi_l = hi_l < kw_hi ? hi_l : kw_hi;
+            const bool has = lo_l <= hi_l;
+            kb = uniform_u64(wave_min_u64(has ? lo_l : ~0ull));
+            ke = uniform_u64(wave_max_u64(has ? hi_l : 0ull));
+        }
+    }
+    __syncthreads();  // busy cleared
+    if (lane == 0 && kb <= ke)
+        atomicOr(&busy, 1u);
+    __syncthreads();
+    if (busy == 0)  // no pair of the group in this window: skip its records
+        return;
+    {
+        const uint32_t rec_bytes = ((uint32_t)((b.y2 - b.y1) >> 5) + 1u) * 16u;
+        const __amdgpu_buffer_rsrc_t rs =
+            __builtin_amdgcn_make_buffer_rsrc(b.words, (short)0, (int)rec_bytes, 0x00020000);
+        const uint32_t base = (uint32_t)((Y0 - b.y1) >> 5) * 16u;  // < 2^27
+        for (uint32_t r = tid; r < EKW_REC; r += EKW_THREADS)
+            win[r] = __builtin_amdgcn_raw_buffer_load_b128(rs, base + r * 16u, 0, 0);
+        if (tid == 0)
+            win[EKW_REC] = u32x4{0u, 0u, 0u, 0u};
+    }
+    __syncthreads();
+    if (kb > ke)
+        return;
+    // lane l walks the k of the tile's x l in this window (a window holds
+    // m 2^17 / Y0^2 of them: a few to thousands), reciprocals per pair
+    // (k <= m / Y0 < 2^31: 32-bit k and counts)
+    const RecLds src{win, EKW_REC};
+    const double ny0 = -(double)Y0, mf = (double)m_l;
+    const uint32_t k0 = (uint32_t)lo_l;
+    const uint32_t cnt = lo_l <= hi_l ? (uint32_t)(hi_l - lo_l) + 1u : 0u;
+    const uint32_t cmax = (uint32_t)uniform_u64(wave_max_u64(cnt));
+    uint32_t dp = 0, dn = 0;
+    uint64_t ms = 0;
+    for (uint32_t j = 0; j < cmax; j += EKW_UNROLL) {
+        K2Batch<EKW_UNROLL> t;
+#pragma unroll
+        for (int u = 0; u < EKW_UNROLL; ++u) {
+            const uint32_t o = (uint32_t)fma(mf, rcp_up((double)(k0 + j + (uint32_t)u)), ny0);
+            t.off[u] = j + (uint32_t)u < cnt ? o : OFF_NONE;
+        }
+#pragma unroll
+        for (int u = 0; u < EKW_UNROLL; ++u)
+            t.rec[u] = src(t.off[u]);
+        k2_consume<EKW_UNROLL>(t, dp, dn, ms);
+    }
+    const uint64_t mine = ms + (uint64_t)(int64_t)(int32_t)(dp - dn);
+    if (lane < nx && mine)
+        atomicAdd((unsigned long long *)&q.S[g0 + lane], (unsigned long long)mine);
+}
+
+hipError_t launch_ek_window(const QueryArgs &q, const BlockArgs &b, uint64_t ystart,
+                            uint64_t yend, hipStream_t s)
+{
+    const uint32_t ngroups = (q.ntiles + EKW_TILES - 1) / EKW_TILES;
+    const uint32_t nwin = (uint32_t)((yend - ystart + EKW_Y - 1) / EKW_Y);
+    hipLaunchKernelGGL(k_ek_window, dim3(nwin * ngroups), dim3(EKW_THREADS), 0, s, q, b, ystart,
+                       yend, ngroups);
     return hipGetLastError();
 }
 

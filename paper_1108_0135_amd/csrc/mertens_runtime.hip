@@ -202,6 +202,10 @@ struct Tuning {
     uint32_t update_window = 0;
     uint64_t window_ymax = 1ull << 30;
     uint32_t rl_fast = 1;
+    // explicit-k pairs with quotients in [2^band_lo, 2^band_hi) are summed
+    // y-major from LDS windows of the records (k_ek_window), the rest by the
+    // persistent update (band_lo = 0: none)
+    uint32_t band_lo = 20, band_hi = 28;
     // x with floor(n/x) >= 2^wide_bits go through the 128-bit wide entries
     // (64: exactly those that need more than 64 bits)
     uint32_t wide_bits = 64;
@@ -211,6 +215,18 @@ struct Tuning {
     bool graph = false;  // replay one captured hipGraph per block
     uint64_t block_auto = 1ull << 30;  // block length when mertens_init gets block = 0
 };
+
+// The band of explicit-k quotients that block [y1, y2] sums y-major, as
+// the window range [ys, ye): none when the band is off or misses the block,
+// or when its windows would not start at a multiple of their length.
+bool band_of(const Tuning &t, uint64_t y1, uint64_t y2, uint64_t &ys, uint64_t &ye)
+{
+    if (t.band_lo < EKW_SHIFT || t.band_hi <= t.band_lo || t.band_hi > 31)
+        return false;
+    ys = std::max<uint64_t>(1ull << t.band_lo, y1);
+    ye = std::min<uint64_t>(1ull << t.band_hi, y2 + 1);
+    return ys < ye && ys % (1ull << EKW_SHIFT) == 0;
+}
 
 #ifndef MERTENS_KERNEL_SHA256
 #define MERTENS_KERNEL_SHA256 ""
@@ -833,13 +849,21 @@ struct Batch {
     }
 
     // update prep and item prefix, [event], persistent update
-    int update_block(const BlockArgs &b, uint32_t grid, hipStream_t s, hipEvent_t mid) const
+    // band: the tuning whose band applies (nullptr: none, e.g. under graph
+    // capture, where b holds no host values of the block)
+    int update_block(const BlockArgs &b, uint32_t grid, hipStream_t s, hipEvent_t mid,
+                     const Tuning *band = nullptr) const
     {
-        HIPCHK(launch_update_prep(args, b, s));
+        uint64_t ys = 0, ye = 0;
+        const bool use = band && band_of(*band, b.y1, b.y2, ys, ye);
+        const uint32_t wa = use ? band->band_lo : 0u, wb = use ? band->band_hi : 0u;
+        HIPCHK(launch_update_prep(args, b, s, wa, wb));
         HIPCHK(launch_scan_items(args, s));
         if (mid)
             HIPCHK(hipEventRecord(mid, s));
-        HIPCHK(launch_update(args, b, grid, s));
+        HIPCHK(launch_update(args, b, grid, s, wa, wb));
+        if (use)
+            HIPCHK(launch_ek_window(args, b, ys, ye, s));
         HIPCHK(launch_wide_prep(args, b, s));
         HIPCHK(launch_wide_update(args, b, s));
         return 0;
@@ -1213,7 +1237,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
                 const BlockArgs bw = g.ss.window_of(b, ua, std::min(ua + W - 1, y2), w);
                 HIPCHK(launch_block_set(SieveState::params_of(bw),
                                         const_cast<BlockParams *>(bw.bp), s));
-                RCCHK(bt.update_block(bw, grid, s, w == 0 ? g.events[ev + 3] : nullptr));
+                RCCHK(bt.update_block(bw, grid, s, w == 0 ? g.events[ev + 3] : nullptr, &g.tune));
                 if (g.tune.progress) {  // windows of a heavy block report one by one
                     if (!g.progress_ev)
                         HIPCHK(hipEventCreateWithFlags(&g.progress_ev, hipEventDisableTiming));
@@ -1225,7 +1249,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
                 }
             }
         } else {
-            RCCHK(bt.update_block(b, grid, s, g.events[ev + 3]));
+            RCCHK(bt.update_block(b, grid, s, g.events[ev + 3], &g.tune));
         }
         HIPCHK(hipEventRecord(g.events[ev + 4], s));
         if (ahead)
@@ -1381,7 +1405,7 @@ int serve_lane_step(ServeLane &ln, uint64_t B)
     const uint32_t grid = update_grid(g.ncu, g.tune);
     for (auto &sb : ln.batches)
         if (sb->open)
-            RCCHK(sb->b.update_block(b, grid, s, nullptr));
+            RCCHK(sb->b.update_block(b, grid, s, nullptr, &g.tune));
 
     // bookkeeping: which queries have now seen every block they need
     std::vector<std::pair<ServeBatch *, std::vector<uint32_t>>> done;
@@ -2142,6 +2166,11 @@ int mertens_set_param(const char *key, double value)
         if (!(value == 0.0 || value == 1.0))
             return MERTENS_EINVAL;
         g.tune.rl_fast = (uint32_t)value;
+    } else if (!strcmp(key, "band_lo") || !strcmp(key, "band_hi")) {
+        // log2 of the band's ends; 0 (band_lo): no band
+        if (!(value == 0.0 || (value >= EKW_SHIFT && value <= 31)) || value != (double)(int)value)
+            return MERTENS_EINVAL;
+        (key[5] == 'l' ? g.tune.band_lo : g.tune.band_hi) = (uint32_t)value;
     } else if (!strcmp(key, "update_window")) {
         if (!(value == 0.0 || (value >= 17 && value <= 40)) || value != (double)(int)value)
             return MERTENS_EINVAL;
@@ -2207,6 +2236,10 @@ int mertens_get_param(const char *key, double *value)
         *value = t.rl_fast;
     else if (!strcmp(key, "update_window"))
         *value = t.update_window;
+    else if (!strcmp(key, "band_lo"))
+        *value = t.band_lo;
+    else if (!strcmp(key, "band_hi"))
+        *value = t.band_hi;
     else if (!strcmp(key, "sieve_ahead"))
         *value = t.sieve_ahead;
     else if (!strcmp(key, "waves_per_cu"))

@@ -176,7 +176,8 @@ def set_param(key: str, value: float) -> None:
 
 
 TUNING_KEYS = ["tuned", "u_scale", "beta", "ychunk", "kchunk", "kbal", "waves_per_cu", "graph",
-               "block_auto", "sieve_ahead", "update_window", "bucket_min", "rl_fast", "wide_bits"]
+               "block_auto", "sieve_ahead", "update_window", "bucket_min", "rl_fast", "wide_bits",
+               "band_lo", "band_hi"]
 
 
 def get_param(key: str) -> float:

@@ -142,6 +142,12 @@ def test_n1e12_and_byproducts(mt):
     (10**8, 1 << 24, {"bucket_min": 1}),
     # the tested run-length path with a small update grid
     (3 * 10**7, 1 << 20, {"rl_fast": 0, "waves_per_cu": 4}),
+    # explicit-k pairs summed y-major from LDS windows: off; over every y
+    # from 2^17 (one window per block); a band that starts and ends inside
+    # blocks of 2^20 y
+    (10**8, 1 << 24, {"band_lo": 0}),
+    (10**8, 1 << 17, {"band_lo": 17, "band_hi": 31}),
+    (2 * 10**8, 1 << 20, {"band_lo": 18, "band_hi": 26, "sieve_ahead": 1}),
 ])
 def test_n1e12_invariance(mt, u, block, params):
     g = GOLDEN["n1e12"]
