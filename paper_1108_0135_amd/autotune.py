@@ -5,8 +5,10 @@ Coordinate search through the C ABI on two calibration workloads:
 * stage 1, the single query M(10^16) with u = 5*10^10 and y-blocks of 2^30:
   ``beta`` (split of each x's sum between the run-length part and the
   explicit k part), the work-item sizes ``ychunk`` / ``kchunk``, the
-  persistent update grid ``waves_per_cu`` and ``graph`` (one captured
-  hipGraph of the block pipeline replayed per block, or direct launches);
+  persistent update grid ``waves_per_cu``, the band ``band_lo`` /
+  ``band_hi`` of explicit-k reads summed y-major from LDS windows, and
+  ``graph`` (one captured hipGraph of the block pipeline replayed per
+  block, or direct launches);
 * stage 2, the batched workload (256 n log-uniform in [1e13, 1e17], seed 0,
   plus 1e16 and 1e17) with automatic u and block: ``u_scale`` (automatic
   u = u_scale * (sum of n)^(2/3): the sieve costs ~u, the update
@@ -44,6 +46,8 @@ STAGE1 = {
     "ychunk": [8192, 16384, 32768],
     "kchunk": [512, 1024, 2048],
     "waves_per_cu": [8, 12, 16],
+    "band_lo": [0, 19, 21],
+    "band_hi": [26, 27, 29],
     "graph": [0, 1],
 }
 STAGE2 = {

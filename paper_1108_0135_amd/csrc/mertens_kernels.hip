@@ -2451,9 +2451,8 @@ hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, 
 }
 
 // Explicit-k pairs of the band [2^wa, 2^wb), y-major: one workgroup per
-// (window of EKW_Y y, group of EKW_TILES tiles), windows of one band in
-// order, the groups of one window consecutive (they share its records in
-// L2).  The window's records are staged in LDS with coalesced loads; each
+// (group of EKW_TILES tiles, window of EKW_Y y), the groups of one window
+// consecutive in dispatch order (they share its records in L2).  The window's records are staged in LDS with coalesced loads; each
 // wave takes one tile and, for its x, the k whose quotient lies in the
 // window, k in [floor(m / (Y0 + EKW_Y)) + 1, floor(m / Y0)] (within the
 // block's k range), walked 8 x 8 as in k_item_2d_fast with the records read
@@ -2481,13 +2480,12 @@ __device__ inline uint32_t div_small(uint32_t a, uint32_t d)
 }
 
 __global__ __launch_bounds__(EKW_THREADS) void k_ek_window(QueryArgs q, BlockArgs b_in,
-                                                           uint64_t ystart, uint64_t yend,
-                                                           uint32_t ngroups)
+                                                           uint64_t ystart, uint64_t yend)
 {
     __shared__ u32x4 win[EKW_REC + 1];
     __shared__ uint32_t busy;
     const BlockArgs b = load_block(b_in);
-    const uint32_t w = blockIdx.x / ngroups, grp = blockIdx.x % ngroups;
+    const uint32_t w = blockIdx.y, grp = blockIdx.x;
     const uint64_t Y0 = ystart + (uint64_t)w * EKW_Y;
     if (Y0 < b.y1 || Y0 > b.y2 || Y0 >= yend)
         return;
@@ -2568,10 +2566,15 @@ __global__ __launch_bounds__(EKW_THREADS) void k_ek_window(QueryArgs q, BlockArg
 hipError_t launch_ek_window(const QueryArgs &q, const BlockArgs &b, uint64_t ystart,
                             uint64_t yend, hipStream_t s)
 {
+    // grid: tile groups along x, windows along y (each dimension's count of
+    // work-items must stay below 2^32; a one-dimensional grid of both would
+    // pass it for large batches)
     const uint32_t ngroups = (q.ntiles + EKW_TILES - 1) / EKW_TILES;
     const uint32_t nwin = (uint32_t)((yend - ystart + EKW_Y - 1) / EKW_Y);
-    hipLaunchKernelGGL(k_ek_window, dim3(nwin * ngroups), dim3(EKW_THREADS), 0, s, q, b, ystart,
-                       yend, ngroups);
+    if ((uint64_t)ngroups * EKW_THREADS >= (1ull << 32) || nwin >= (1u << 16))
+        return hipErrorInvalidConfiguration;
+    hipLaunchKernelGGL(k_ek_window, dim3(ngroups, nwin), dim3(EKW_THREADS), 0, s, q, b, ystart,
+                       yend);
     return hipGetLastError();
 }
 
