@@ -46,10 +46,10 @@ METRIC = "sieved y/sec through update; batched vs plain M(n) queries/sec, 1 GPU,
 HBM_PEAK_GBS = 8000.0
 CU, CLOCK_GHZ, LANES = 256, 2.4, 64
 INT_VALU_PEAK_TOPS = CU * LANES * CLOCK_GHZ / 1000.0  # 39.3 T int32 lane-ops/s
-# algorithmic cost of one exact quotient floor(m/d) with its accumulation, in
-# full-rate VALU lane-ops: estimate (fp64 multiply), truncate, residual (fma),
-# near-integer offset and test (add, compare), accumulate (add)
-OPS_PER_QUOTIENT = 6
+# algorithmic cost of one pair of the update, in full-rate VALU lane-ops: the
+# quotient floor(m/d) (one fused multiply-add with a reciprocal of d) and its
+# signed accumulation (one multiply-add); fp64 fma is full rate on MI355X
+OPS_PER_QUOTIENT = 2
 RECORD_BYTES = 16  # one sieve record: M(y) checkpoint and mu bits of 32 y
 # the method's own need per explicit-k pair: one int32 M(y) read at a random y
 GATHER_BYTES = 4
@@ -230,44 +230,68 @@ def workload_default(args, mt) -> dict:
     seq = mt.stats()
     mt.set_param("sieve_ahead", ahead)
     launches = seq["update_launches"]
-    upd_ms_launch = seq["ms_update"] / launches
+    # the update step of a block is the persistent k_update and, where the
+    # band applies (block 0 here), the y-major k_ek_window after it
+    band_ms = seq.get("ms_band", 0.0)
+    band_q = seq.get("band_quotients", 0.0)
+    upd_ms_total = seq["ms_update"] - band_ms
+    upd_ms_launch = upd_ms_total / launches
     sieve_ms_launch = seq["ms_sieve"] / seq["sieve_launches"]
-    quot = seq["rl_quotients"] + seq["k_quotients"]
+    k_upd = seq["k_quotients"] - band_q  # explicit-k pairs k_update takes
+    quot = seq["rl_quotients"] + k_upd
     upd_tops = quot / launches * OPS_PER_QUOTIENT / (upd_ms_launch * 1e-3) / 1e12
-    # update: the method's HBM bytes = one int32 M(y) per explicit-k pair (a
-    # random read) + the run-length masks (8 bytes per 32 y) read once per
-    # 64-x tile over y <= Y; the record-layout view counts the 16-byte record
-    # this build reads per explicit-k pair instead
+    # k_update's HBM view: the method's bytes = one int32 M(y) per explicit-k
+    # pair (a random read) + the run-length masks (8 bytes per 32 y) read once
+    # per 64-x tile over y <= Y; the record-layout view counts the 16-byte
+    # record this build reads per explicit-k pair instead
     mask_bytes = 0.25 * seq["sum_Y"] / 64
-    upd_bytes = (GATHER_BYTES * seq["k_quotients"] + mask_bytes) / launches
+    upd_bytes = (GATHER_BYTES * k_upd + mask_bytes) / launches
     upd_gbs = upd_bytes / (upd_ms_launch * 1e-3) / 1e9
-    rec_bytes = (RECORD_BYTES * seq["k_quotients"] + mask_bytes) / launches
+    rec_bytes = (RECORD_BYTES * k_upd + mask_bytes) / launches
     rec_gbs = rec_bytes / (upd_ms_launch * 1e-3) / 1e9
     # sieve: the records it writes, 0.5 byte per y
     sieve_gbs = (sieved / seq["sieve_launches"]) * 0.5 / (sieve_ms_launch * 1e-3) / 1e9
-    if seq["ms_update"] >= seq["ms_sieve"]:
-        roof = {"kernel": "k_update", "bound": "hbm", "achieved": upd_gbs,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": upd_gbs / HBM_PEAK_GBS,
+    upd_view = {"kernel": "k_update", "bound": "alu", "achieved": upd_tops,
+                "peak": INT_VALU_PEAK_TOPS, "unit": "TOP/s", "frac": upd_tops / INT_VALU_PEAK_TOPS,
                 "traffic": traffic_per_launch("k_update"),
-                "algorithmic_bytes_per_launch": upd_bytes,
-                "bytes_rule": (f"{GATHER_BYTES} B (one int32 M(y)) per explicit-k pair + 8 B "
-                               f"of mu masks per 32 y per 64-x tile of the run-length part"),
+                "ops_rule": (f"{OPS_PER_QUOTIENT} lane-ops per pair (quotient by fused "
+                             f"multiply-add with a reciprocal, signed accumulation), run-length "
+                             f"pairs + the explicit-k pairs outside the band; peak = 256 CUs x "
+                             f"64 lanes x 2.4 GHz"),
                 "avg_launch_ms": upd_ms_launch, "launches": launches,
-                "quotients_per_launch": quot / launches,
+                "pairs_per_launch": quot / launches,
+                "hbm_view": {"achieved": upd_gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": upd_gbs / HBM_PEAK_GBS, "bytes_per_launch": upd_bytes,
+                             "rule": (f"{GATHER_BYTES} B (one int32 M(y)) per explicit-k pair + "
+                                      f"8 B of mu masks per 32 y per 64-x tile of the "
+                                      f"run-length part")},
                 "record_layout_view": {"achieved": rec_gbs, "frac": rec_gbs / HBM_PEAK_GBS,
                                        "bytes_per_launch": rec_bytes,
-                                       "rule": f"{RECORD_BYTES} B record per explicit-k pair"},
-                "alu_view": {"achieved_Tops": upd_tops, "peak_Tops": INT_VALU_PEAK_TOPS,
-                             "frac": upd_tops / INT_VALU_PEAK_TOPS,
-                             "ops_per_quotient": OPS_PER_QUOTIENT}}
+                                       "rule": f"{RECORD_BYTES} B record per explicit-k pair"}}
+    sieve_view = {"kernel": "k_sieve", "bound": "hbm", "achieved": sieve_gbs,
+                  "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sieve_gbs / HBM_PEAK_GBS,
+                  "traffic": traffic_per_launch("k_sieve"), "avg_launch_ms": sieve_ms_launch,
+                  "launches": seq["sieve_launches"],
+                  "rule": "0.5 B of records written per y (VALU and LDS atomics bound it)"}
+    band_view = None
+    if band_ms > 0 and band_q > 0:
+        band_tops = band_q * OPS_PER_QUOTIENT / (band_ms * 1e-3) / 1e12
+        band_view = {"kernel": "k_ek_window", "ms": band_ms, "pairs": band_q,
+                     "alu_achieved_TOPs": band_tops,
+                     "alu_frac": band_tops / INT_VALU_PEAK_TOPS,
+                     "hbm_view_GBs": GATHER_BYTES * band_q / (band_ms * 1e-3) / 1e9,
+                     "rule": (f"{OPS_PER_QUOTIENT} lane-ops and {GATHER_BYTES} B per explicit-k "
+                              f"pair whose M(y) read lies in the band (records staged in LDS)")}
+    if upd_ms_total >= seq["ms_sieve"]:
+        roof = dict(upd_view)
+        roof["others"] = {"k_sieve": sieve_view, "k_ek_window": band_view}
     else:
-        roof = {"kernel": "k_sieve", "bound": "hbm", "achieved": sieve_gbs,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": sieve_gbs / HBM_PEAK_GBS,
-                "traffic": traffic_per_launch("k_sieve"), "avg_launch_ms": sieve_ms_launch,
-                "launches": seq["sieve_launches"]}
+        roof = dict(sieve_view)
+        roof["others"] = {"k_update": upd_view, "k_ek_window": band_view}
     roof["traffic_unit"] = ("bytes per launch between L2 and memory (rocprofv3 FETCH_SIZE x2 + "
                             "WRITE_SIZE x1, calibrated on a plain copy)")
-    roof["in_turn_ms"] = {k: seq[k] for k in ("ms_sieve", "ms_prep", "ms_update", "ms_total")}
+    roof["in_turn_ms"] = {k: seq[k] for k in ("ms_sieve", "ms_prep", "ms_update", "ms_band",
+                                               "ms_total")}
     line = {
         "metric": METRIC,
         "value": sieved / (ms_step * 1e-3),
@@ -288,7 +312,8 @@ def workload_default(args, mt) -> dict:
         "plain_queries_per_s": 1000.0 / ms_step,
         "kernel_ms": {k: avg(k) for k in ("ms_sieve", "ms_scan", "ms_prep", "ms_update",
                                           "ms_finalize", "ms_total")},
-        "quotients": {"run_length": st["rl_quotients"], "explicit_k": st["k_quotients"]},
+        "quotients": {"run_length": st["rl_quotients"], "explicit_k": st["k_quotients"],
+                      "explicit_k_band": st["band_quotients"]},
         "roofline": roof,
     }
     # the byproduct M(10^16 // 10^4) = M(10^12), checked against the oracle

@@ -247,6 +247,8 @@ int mertens_get_param(const char *key, double *value);
  *  15 explicit k quotients taken (= M(y) gathers)
  *  16 bucket entries listed    17 ms bucket fill pass    18 bucketed prime visits
  *  19 ms bucket regrouping pass   (16-19: mertens_interval only, 0 after a query)
+ *  20 ms of the y-major band kernel (part of 9)
+ *  21 explicit k quotients taken by it (part of 15)
  * Kernel times are HIP-event intervals on the library's stream.
  */
 int mertens_stats(double *vals, int cap);

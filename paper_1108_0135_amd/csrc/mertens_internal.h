@@ -135,7 +135,8 @@ struct QueryArgs {
     uint32_t *tile_mode, *tile_nmu;
     uint64_t *tile_items;               // items per tile, then exclusive prefix (ntiles+1)
     uint32_t *counter;                  // persistent work counter
-    uint64_t *pair_stats;               // [0] y-side visits, [1] k pairs
+    uint64_t *pair_stats;               // [0] y-side visits, [1] k pairs, [2] run-length
+                                        // pairs, [3] explicit-k pairs, [4] of those, the band's
     // Wide arguments (n >= 2^64): per query the high word of n and the number
     // xb of leading x whose m = floor(n/x) >= 2^wide_bits.  Those x take
     // the wide entries below (m in 128 bits); their plain slots do no work.

@@ -1635,6 +1635,14 @@ __device__ inline double rcp_1ulp(double y)
     return fma(r, e, r);
 }
 
+// 1/k raised by four units in the last place (rcp_1ulp, then +4 in the
+// bits): for m < 2^48 the product m * rcp_up(k) rounded once lies in
+// [m/k, (m/k)(1 + 2^-49.5)], whose floor is floor(m/k) (see rl_pass).
+__device__ inline double rcp_up(double k)
+{
+    return __longlong_as_double(__double_as_longlong(rcp_1ulp(k)) + 4);
+}
+
 // One pass of RL_XS x (m as fp64 in mf, NaN past the tile's end) over the
 // compacted entries.
 // * FAST (every m < 2^48, every y <= Y): with r within one ulp of 1/y
@@ -1756,6 +1764,53 @@ __device__ inline double wave_multi_sum16(double (&a)[RL_XS])
     return v;
 }
 
+// The FAST23 pass (see rl_pass) over 32 x at once, for sub-chunks where
+// every x of the tile qualifies: one reciprocal and entry decode per 32
+// pairs instead of per 16.
+constexpr int RL_XS2 = 32;
+
+__device__ inline void rl_pass_fast23_32(const uint16_t *ent, uint32_t total, uint32_t wb0,
+                                         const double (&mf)[RL_XS2], int (&acc32)[RL_XS2])
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int i = 0; i < RL_XS2; ++i)
+        acc32[i] = 0;
+    for (uint32_t t = lane; t < total; t += 64) {
+        const uint32_t e = ent[t];
+        const double ru = rcp_up((double)(wb0 + (e & 0x0FFFu)));
+        int si = (e & 0x8000u) ? -1 : 1;
+        __asm__ volatile("" : "+v"(si));  // keep the multiply-add (see rl_pass)
+#pragma unroll
+        for (int i = 0; i < RL_XS2; ++i) {
+            const double tq = fma(mf[i], ru, RL_MAGIC);
+            acc32[i] += __mul24((int)(uint32_t)__double_as_longlong(tq), si);
+        }
+    }
+}
+
+// Sum of each of 32 int values over the wave, by halving exchanges: after
+// the xor-32/16/8/4/2 steps lane l holds a partial sum of value l >> 1 only,
+// and the xor-1 step completes it on both lanes of each pair.
+__device__ inline int wave_multi_sum32_i(int (&a)[RL_XS2])
+{
+    const uint32_t lane = lane_id();
+#pragma unroll
+    for (int h = 16; h >= 1; h >>= 1) {
+        const int o = h * 2;  // 32, 16, 8, 4, 2
+        const bool up = (lane & (uint32_t)o) != 0;
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const int send = up ? a[j] : a[j + h];
+            const int keep = up ? a[j + h] : a[j];
+            a[j] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    int v = a[0];
+    v += __shfl_xor(v, 1, 64);
+    return v;
+}
+
 // Run-length part, lanes over y.  The item's y range is taken in sub-chunks
 // of 4096 aligned y: the squarefree y of a sub-chunk are compacted into LDS
 // (12-bit offset | sign << 15) and each lane takes every 64th entry against
@@ -1774,6 +1829,14 @@ __device__ inline void mu_item_lanes(const QueryArgs &q, const BlockArgs &b, uin
     const uint32_t qd = lane & 3u, xi = (lane >> 2) + 16u * qd;
     double mine = 0.0;
     uint64_t nq = 0;
+    // the tile's largest m and smallest Y (32-x FAST23 passes need every x
+    // to qualify)
+    uint64_t t_mmax, t_ymin;
+    {
+        const bool ok = lane < nx;
+        t_mmax = uniform_u64(wave_max_u64(ok ? q.x_m[g0 + lane] : 0ull));
+        t_ymin = uniform_u64(wave_min_u64(ok ? q.x_Y[g0 + lane] : ~0ull));
+    }
     for (uint64_t sb = cs & ~63ull; sb <= ce; sb += RL_ENT_SPAN) {
         const uint64_t ss = sb > cs ? sb : cs;
         const uint64_t se = (ce - sb) < RL_ENT_SPAN - 1 ? ce : sb + RL_ENT_SPAN - 1;
@@ -1806,6 +1869,35 @@ __device__ inline void mu_item_lanes(const QueryArgs &q, const BlockArgs &b, uin
         }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
+
+        if (q.rl_fast && se <= t_ymin && (double)t_mmax < RL_M_EXACT &&
+            (double)t_mmax < RL_Q23 * (double)ss) {
+            // two passes of 32 x; lane l then holds x 32 p + (l >> 1), and the
+            // lane that sums x in the 16-x layout takes it over
+#pragma unroll 1
+            for (uint32_t p = 0; p < 2; ++p) {
+                const uint32_t xs = p * RL_XS2;
+                if (xs >= nx)
+                    break;
+                double mf[RL_XS2];
+                int acc32[RL_XS2];
+#pragma unroll
+                for (int i = 0; i < RL_XS2; ++i) {
+                    const bool ok = xs + (uint32_t)i < nx;
+                    const uint64_t mi = ok ? uniform_u64(q.x_m[g0 + xs + i]) : 0;
+                    // NaN past the tile's end: the result's low word is 0
+                    mf[i] = ok ? (double)mi : __longlong_as_double(0x7ff8000000000000ll);
+                }
+                rl_pass_fast23_32(ent, total, (uint32_t)sb, mf, acc32);
+                const int v = wave_multi_sum32_i(acc32);
+                const int w = __shfl(v, (int)(2u * (xi - xs)) & 63, 64);
+                if ((xi >> 5) == p)
+                    mine += (double)w;
+                const uint32_t nxs = (nx - xs) < (uint32_t)RL_XS2 ? nx - xs : (uint32_t)RL_XS2;
+                nq += lane == 0 ? (uint64_t)total * nxs : 0;
+            }
+            continue;
+        }
 
 #pragma unroll 1
         for (uint32_t p = 0; p < 4; ++p) {
@@ -2051,13 +2143,6 @@ __device__ inline uint64_t M_sum_masked32(const uint64_t *__restrict__ words,
 // 8 k-lanes and leave with one 64-lane atomic per item.
 constexpr uint32_t K2D_SUB = 512;  // k per reciprocal sub-chunk (4 KB of LDS)
 
-// 1/k raised by four units in the last place (rcp_1ulp, then +4 in the
-// bits): for m < 2^48 the product m * rcp_up(k) rounded once lies in
-// [m/k, (m/k)(1 + 2^-49.5)], whose floor is floor(m/k) (see rl_pass).
-__device__ inline double rcp_up(double k)
-{
-    return __longlong_as_double(__double_as_longlong(rcp_1ulp(k)) + 4);
-}
 
 // Record loads in flight per lane and batch of the walk below (8 x 8
 // lanes, 16 batches: 128 consecutive k per x in flight).  Measured at
@@ -2544,6 +2629,11 @@ __global__ __launch_bounds__(EKW_THREADS) void k_ek_window(QueryArgs q, BlockArg
     const uint32_t k0 = (uint32_t)lo_l;
     const uint32_t cnt = lo_l <= hi_l ? (uint32_t)(hi_l - lo_l) + 1u : 0u;
     const uint32_t cmax = (uint32_t)uniform_u64(wave_max_u64(cnt));
+    {
+        const uint64_t wp = wave_sum_u64(cnt);
+        if (lane == 0 && wp)
+            atomicAdd((unsigned long long *)&q.pair_stats[4], (unsigned long long)wp);
+    }
     uint32_t dp = 0, dn = 0;
     uint64_t ms = 0;
     for (uint32_t j = 0; j < cmax; j += EKW_UNROLL) {

@@ -842,7 +842,7 @@ struct Batch {
         q.kchunk = t.kchunk;
         q.rl_fast = t.rl_fast;
         q.kbal = t.kbal;
-        HIPCHK(launch_zero_u64(pair_stats.as<uint64_t>(), 4, s));
+        HIPCHK(launch_zero_u64(pair_stats.as<uint64_t>(), 5, s));
         HIPCHK(launch_plan(q, s));
         HIPCHK(launch_wide_plan(q, s));
         return 0;
@@ -852,7 +852,7 @@ struct Batch {
     // band: the tuning whose band applies (nullptr: none, e.g. under graph
     // capture, where b holds no host values of the block)
     int update_block(const BlockArgs &b, uint32_t grid, hipStream_t s, hipEvent_t mid,
-                     const Tuning *band = nullptr) const
+                     const Tuning *band = nullptr, hipEvent_t band_ev = nullptr) const
     {
         uint64_t ys = 0, ye = 0;
         const bool use = band && band_of(*band, b.y1, b.y2, ys, ye);
@@ -862,6 +862,8 @@ struct Batch {
         if (mid)
             HIPCHK(hipEventRecord(mid, s));
         HIPCHK(launch_update(args, b, grid, s, wa, wb));
+        if (band_ev)  // between the persistent update and the band's kernel
+            HIPCHK(hipEventRecord(band_ev, s));
         if (use)
             HIPCHK(launch_ek_window(args, b, ys, ye, s));
         HIPCHK(launch_wide_prep(args, b, s));
@@ -996,7 +998,7 @@ struct Ctx {
     std::vector<uint64_t> last_L, last_g0;
     std::vector<int64_t> last_j;  // index in the batch, -1 for n = 0
     bool last_valid = false;
-    double stats[20] = {0};
+    double stats[22] = {0};
     hipEvent_t progress_ev = nullptr;
     std::vector<hipEvent_t> events;
     Server srv;
@@ -1136,12 +1138,13 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     RCCHK(g.ss.ensure_blocks(B, slots));
     const uint32_t grid = update_grid(g.ncu, g.tune);
 
-    // timing events: [0] start, [1]/[2] around finalize, then five per block
+    // timing events: [0] start, [1]/[2] around finalize, then six per block
     // in a ring of EV_RING blocks (a block's times are added up before its
-    // slot is reused)
+    // slot is reused): sieve start and end, prep start, update start, update
+    // end, and between the persistent update and the band's kernel
     const uint64_t EV_RING = g.noalloc ? NOALLOC_EV_RING : 4096;
     const uint64_t nring = std::min<uint64_t>(nblocks, EV_RING);
-    if (!event_at(3 + 5 * nring) || !slot_events(slots)) {
+    if (!event_at(3 + 6 * nring) || !slot_events(slots)) {
         set_error_text("hipEventCreate failed");
         return MERTENS_EIO;
     }
@@ -1153,11 +1156,12 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     if (ahead)
         HIPCHK(hipStreamWaitEvent(ss, g.events[0], 0));  // after the plan
     RCCHK(g.ss.reset_carry(ss));
-    double t_sieve = 0, t_scan = 0, t_prep = 0, t_upd = 0;
+    double t_sieve = 0, t_scan = 0, t_prep = 0, t_upd = 0, t_band = 0;
     auto add_times = [&](size_t m) {
         t_sieve += elapsed(m, m + 1);
         t_prep += elapsed(m + 2, m + 3);
         t_upd += elapsed(m + 3, m + 4);
+        t_band += elapsed(m + 5, m + 4);
     };
     if (g.tune.graph) {
         // one captured graph of the whole block pipeline, replayed per block;
@@ -1214,7 +1218,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
         const uint64_t y2 = std::min(y1 + B - 1, ymax);
         const uint32_t slot = (uint32_t)(bi % slots);
         const BlockArgs b = g.ss.make_block(y1, y2, slot);
-        const size_t ev = 3 + 5 * (size_t)(bi % EV_RING);
+        const size_t ev = 3 + 6 * (size_t)(bi % EV_RING);
         if (bi >= EV_RING) {  // the slot's previous block: wait for it, keep its times
             HIPCHK(hipEventSynchronize(g.events[ev + 4]));
             add_times(ev);
@@ -1237,7 +1241,8 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
                 const BlockArgs bw = g.ss.window_of(b, ua, std::min(ua + W - 1, y2), w);
                 HIPCHK(launch_block_set(SieveState::params_of(bw),
                                         const_cast<BlockParams *>(bw.bp), s));
-                RCCHK(bt.update_block(bw, grid, s, w == 0 ? g.events[ev + 3] : nullptr, &g.tune));
+                RCCHK(bt.update_block(bw, grid, s, w == 0 ? g.events[ev + 3] : nullptr, &g.tune,
+                                      w + 1 == nw ? g.events[ev + 5] : nullptr));
                 if (g.tune.progress) {  // windows of a heavy block report one by one
                     if (!g.progress_ev)
                         HIPCHK(hipEventCreateWithFlags(&g.progress_ev, hipEventDisableTiming));
@@ -1249,7 +1254,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
                 }
             }
         } else {
-            RCCHK(bt.update_block(b, grid, s, g.events[ev + 3], &g.tune));
+            RCCHK(bt.update_block(b, grid, s, g.events[ev + 3], &g.tune, g.events[ev + 5]));
         }
         HIPCHK(hipEventRecord(g.events[ev + 4], s));
         if (ahead)
@@ -1265,9 +1270,9 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     RCCHK(bt.finalize({}, s));
     HIPCHK(hipEventRecord(g.events[2], s));
     res.resize(nq);
-    uint64_t pst[4] = {0, 0, 0, 0};
+    uint64_t pst[5] = {0, 0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(res.data(), bt.out_dev.p, nq * 8, hipMemcpyDeviceToHost, s));
-    HIPCHK(hipMemcpyAsync(pst, bt.pair_stats.p, 32, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(pst, bt.pair_stats.p, 40, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     if (ahead)
         HIPCHK(hipStreamSynchronize(ss));
@@ -1276,7 +1281,7 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     // can exceed the total
     if (!g.tune.graph)
         for (uint64_t bj = nblocks - nring; bj < nblocks; ++bj)
-            add_times(3 + 5 * (size_t)(bj % EV_RING));
+            add_times(3 + 6 * (size_t)(bj % EV_RING));
     g.stats[0] = (double)(ymax + 1);
     g.stats[1] = (double)nblocks;
     g.stats[2] = (double)u;
@@ -1293,6 +1298,8 @@ int run_query(const std::vector<uint64_t> &ns, std::vector<int64_t> &res,
     g.stats[13] = (double)nblocks;
     g.stats[14] = (double)pst[2];
     g.stats[15] = (double)pst[3];
+    g.stats[20] = t_band;
+    g.stats[21] = (double)pst[4];
     for (int i = 16; i < 20; ++i)
         g.stats[i] = 0;
     return 0;
@@ -1704,7 +1711,7 @@ int mertens_init(uint64_t u, uint64_t block)
             g_scratch_dev[g.device] = static_cast<uint8_t *>(ptr);
         }
     }
-    if (rc == 0 && (!event_at(3 + 5 * NOALLOC_EV_RING) || !slot_events(1))) {
+    if (rc == 0 && (!event_at(3 + 6 * NOALLOC_EV_RING) || !slot_events(1))) {
         set_error_text("hipEventCreate failed");
         rc = MERTENS_EIO;
     }
@@ -2263,7 +2270,7 @@ int mertens_stats(double *vals, int cap)
 {
     if (!vals || cap <= 0)
         return 0;
-    const int k = std::min(cap, 20);
+    const int k = std::min(cap, 22);
     for (int i = 0; i < k; ++i)
         vals[i] = g.stats[i];
     return k;

@@ -21,7 +21,7 @@ EINVAL, ENOMEM, ENODEV, ERANGE, EIO, EAGAIN, EINPROGRESS = -22, -12, -19, -34, -
 STAT_NAMES = ["sieved_y", "blocks", "u", "sum_L", "sum_Y", "sum_k", "ms_sieve",
               "ms_scan", "ms_prep", "ms_update", "ms_finalize", "ms_total", "update_launches",
               "sieve_launches", "rl_quotients", "k_quotients", "bucket_entries", "ms_bucket_fill",
-              "bucket_prime_visits", "ms_bucket_regroup"]
+              "bucket_prime_visits", "ms_bucket_regroup", "ms_band", "band_quotients"]
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1108_0135_amd.build`")
