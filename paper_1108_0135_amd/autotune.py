@@ -6,7 +6,8 @@ Coordinate search through the C ABI on two calibration workloads:
   ``beta`` (split of each x's sum between the run-length part and the
   explicit k part), the work-item sizes ``ychunk`` / ``kchunk``, the
   persistent update grid ``waves_per_cu``, the band ``band_lo`` /
-  ``band_hi`` of explicit-k reads summed y-major from LDS windows, and
+  ``band_hi`` of explicit-k reads summed y-major from LDS windows, how many
+  blocks the sieve may run ahead of the update (``sieve_ahead``), and
   ``graph`` (one captured hipGraph of the block pipeline replayed per
   block, or direct launches);
 * stage 2, the batched workload (256 n log-uniform in [1e13, 1e17], seed 0,
@@ -48,6 +49,7 @@ STAGE1 = {
     "waves_per_cu": [8, 12, 16],
     "band_lo": [0, 19, 21],
     "band_hi": [26, 27, 29],
+    "sieve_ahead": [4, 16, 64],
     "graph": [0, 1],
 }
 STAGE2 = {

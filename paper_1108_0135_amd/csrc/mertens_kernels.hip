@@ -1240,8 +1240,15 @@ __global__ __launch_bounds__(UPD_THREADS) void k_update_prep(QueryArgs q, BlockA
             mode = 0;  // the 8 x 8 walk keeps at least 1/kbal of its lanes busy
             uint64_t amax = 0, bmin = ~0ull;
             const bool gap = wa < wb && band_tile(q, b, uniform_u64(wave_max_u64(m)), 0);
-            if (gap)
+            if (gap) {
                 band_gap(m, klo, khi, wa, wb, amax, bmin);
+                // the band's pairs (k_ek_window takes them), for the statistics
+                const uint64_t hl = (m >> wb) + 1, hh = m >> wa;
+                const uint64_t a = klo > hl ? klo : hl, c = khi < hh ? khi : hh;
+                const uint64_t bp = wave_sum_u64(klo <= khi && a <= c ? c - a + 1 : 0ull);
+                if (lane == 0 && bp)
+                    atomicAdd((unsigned long long *)&q.pair_stats[4], (unsigned long long)bp);
+            }
             const KChunks c = k_chunks(tmin, tmax, q.kchunk, gap, amax, bmin);
             nk = c.n_a + c.n_b;
         } else {
@@ -2629,11 +2636,6 @@ __global__ __launch_bounds__(EKW_THREADS) void k_ek_window(QueryArgs q, BlockArg
     const uint32_t k0 = (uint32_t)lo_l;
     const uint32_t cnt = lo_l <= hi_l ? (uint32_t)(hi_l - lo_l) + 1u : 0u;
     const uint32_t cmax = (uint32_t)uniform_u64(wave_max_u64(cnt));
-    {
-        const uint64_t wp = wave_sum_u64(cnt);
-        if (lane == 0 && wp)
-            atomicAdd((unsigned long long *)&q.pair_stats[4], (unsigned long long)wp);
-    }
     uint32_t dp = 0, dn = 0;
     uint64_t ms = 0;
     for (uint32_t j = 0; j < cmax; j += EKW_UNROLL) {
