@@ -198,7 +198,7 @@ def workload_default(args, mt) -> dict:
 
     progress("default workload: M(1e16)")
     mt.init(U_WORK, BLOCK_WORK)
-    ahead = 1 if args.in_turn else 4
+    ahead = 1 if args.in_turn else int(mt.get_param("sieve_ahead"))  # the tuned value
     mt.set_param("sieve_ahead", ahead)
     for _ in range(max(args.warmup, 1)):
         got = int(mt.query([N_WORK])[0])
