@@ -2543,12 +2543,15 @@ hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, 
 }
 
 // Explicit-k pairs of the band [2^wa, 2^wb), y-major: one workgroup per
-// (group of EKW_TILES tiles, window of EKW_Y y), the groups of one window
-// consecutive in dispatch order (they share its records in L2).  The window's records are staged in LDS with coalesced loads; each
+// (group of EKW_TILES tiles, run of EKW_RUN consecutive windows of EKW_Y y),
+// the groups of one run consecutive in dispatch order (they share its
+// records in L2).  Each window's records are staged in LDS with coalesced
+// loads in turn (a window with no pair of the group is skipped); each
 // wave takes one tile and, for its x, the k whose quotient lies in the
 // window, k in [floor(m / (Y0 + EKW_Y)) + 1, floor(m / Y0)] (within the
-// block's k range), walked 8 x 8 as in k_item_2d_fast with the records read
-// from LDS.  Offsets are taken from Y0 (the window is no longer than Y0,
+// block's k range), one lane per x with a reciprocal per pair and the
+// records read from LDS; the lane's sum over the run leaves with one atomic.
+// Offsets are taken from Y0 (the window is no longer than Y0,
 // so the fused quotient rule above holds with y1 = Y0).  Windows start at
 // ystart (a multiple of EKW_Y, at least EKW_Y) and cover [ystart, yend);
 // yend <= 2^31.
@@ -2556,7 +2559,8 @@ constexpr uint32_t EKW_Y = 1u << EKW_SHIFT;
 constexpr uint32_t EKW_REC = EKW_Y / 32;  // 4096 records = 64 KiB
 constexpr int EKW_THREADS = 1024;
 constexpr uint32_t EKW_TILES = EKW_THREADS / 64;
-constexpr int EKW_UNROLL = 8;  // LDS reads per lane and batch
+constexpr int EKW_UNROLL = 4;  // LDS reads per lane and batch (eight spill at 64 VGPRs)
+constexpr uint32_t EKW_RUN = 8;  // consecutive windows per workgroup
 
 // floor(a / d) for a < 2^32, 1 <= d < 2^32: an fp64 estimate (within one
 // of the quotient) and one integer correction.
@@ -2571,87 +2575,89 @@ __device__ inline uint32_t div_small(uint32_t a, uint32_t d)
     return qv;
 }
 
-__global__ __launch_bounds__(EKW_THREADS) void k_ek_window(QueryArgs q, BlockArgs b_in,
+__global__ __launch_bounds__(EKW_THREADS, 8) void k_ek_window(QueryArgs q, BlockArgs b_in,
                                                            uint64_t ystart, uint64_t yend)
 {
     __shared__ u32x4 win[EKW_REC + 1];
-    __shared__ uint32_t busy;
+    // per wave: its largest count of pairs in the window, in two sets used
+    // by alternate windows (a wave may write the next window's flag while
+    // another still reads this one's; reusing a set needs the next barrier,
+    // which every wave reaches only after its reads)
+    __shared__ uint32_t wave_busy[2][EKW_TILES];
     const BlockArgs b = load_block(b_in);
-    const uint32_t w = blockIdx.y, grp = blockIdx.x;
-    const uint64_t Y0 = ystart + (uint64_t)w * EKW_Y;
-    if (Y0 < b.y1 || Y0 > b.y2 || Y0 >= yend)
-        return;
     const uint32_t tid = threadIdx.x, lane = lane_id();
     const uint32_t wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-    if (tid == 0)
-        busy = 0;
-    // this wave's tile and, per x, the k whose quotient lies in the window:
-    // floor(m / (a 2^17)) = floor(floor(m / 2^17) / a)
-    const uint32_t tile = grp * EKW_TILES + wave;
+    // this wave's tile; lane l holds its x l (an empty k range past the tile)
+    const uint32_t tile = blockIdx.x * EKW_TILES + wave;
     uint32_t nx = 0;
-    uint64_t g0 = 0, m_l = 0, lo_l = 1, hi_l = 0, kb = 1, ke = 0;
+    uint64_t g0 = 0, m_l = 0, klo_l = 1, khi_l = 0;
+    bool act = false;
     if (tile < q.ntiles) {
         nx = __builtin_amdgcn_readfirstlane(q.tile_nx[tile]);
         g0 = uniform_u64(q.tile_g0[tile]);
         if (lane < nx) {
             m_l = q.x_m[g0 + lane];
-            lo_l = q.x_klo[g0 + lane];
-            hi_l = q.x_khi[g0 + lane];
+            klo_l = q.x_klo[g0 + lane];
+            khi_l = q.x_khi[g0 + lane];
         }
-        if (band_tile(q, b, uniform_u64(wave_max_u64(m_l)), q.tile_mode[tile])) {
-            const uint32_t mh = (uint32_t)(m_l >> EKW_SHIFT);  // < 2^31
-            const uint32_t a = (uint32_t)(Y0 >> EKW_SHIFT);     // < 2^14 (Y0 < 2^31)
-            const uint64_t kw_hi = div_small(mh, a), kw_lo = (uint64_t)div_small(mh, a + 1) + 1;
-            lo_l = lo_l > kw_lo ? lo_l : kw_lo;
-            hi_l = hi_l < kw_hi ? hi_l : kw_hi;
-            const bool has = lo_l <= hi_l;
-            kb = uniform_u64(wave_min_u64(has ? lo_l : ~0ull));
-            ke = uniform_u64(wave_max_u64(has ? hi_l : 0ull));
-        }
+        act = band_tile(q, b, uniform_u64(wave_max_u64(m_l)), q.tile_mode[tile]);
     }
-    __syncthreads();  // busy cleared
-    if (lane == 0 && kb <= ke)
-        atomicOr(&busy, 1u);
-    __syncthreads();
-    if (busy == 0)  // no pair of the group in this window: skip its records
-        return;
-    {
-        const uint32_t rec_bytes = ((uint32_t)((b.y2 - b.y1) >> 5) + 1u) * 16u;
-        const __amdgpu_buffer_rsrc_t rs =
-            __builtin_amdgcn_make_buffer_rsrc(b.words, (short)0, (int)rec_bytes, 0x00020000);
-        const uint32_t base = (uint32_t)((Y0 - b.y1) >> 5) * 16u;  // < 2^27
-        for (uint32_t r = tid; r < EKW_REC; r += EKW_THREADS)
-            win[r] = __builtin_amdgcn_raw_buffer_load_b128(rs, base + r * 16u, 0, 0);
-        if (tid == 0)
-            win[EKW_REC] = u32x4{0u, 0u, 0u, 0u};
-    }
-    __syncthreads();
-    if (kb > ke)
-        return;
-    // lane l walks the k of the tile's x l in this window (a window holds
-    // m 2^17 / Y0^2 of them: a few to thousands), reciprocals per pair
-    // (k <= m / Y0 < 2^31: 32-bit k and counts)
+    const uint32_t mh = act ? (uint32_t)(m_l >> EKW_SHIFT) : 0u;  // m < 2^48: < 2^31
+    const double mf = (double)m_l;
     const RecLds src{win, EKW_REC};
-    const double ny0 = -(double)Y0, mf = (double)m_l;
-    const uint32_t k0 = (uint32_t)lo_l;
-    const uint32_t cnt = lo_l <= hi_l ? (uint32_t)(hi_l - lo_l) + 1u : 0u;
-    const uint32_t cmax = (uint32_t)uniform_u64(wave_max_u64(cnt));
-    uint32_t dp = 0, dn = 0;
+    const uint32_t rec_bytes = ((uint32_t)((b.y2 - b.y1) >> 5) + 1u) * 16u;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(b.words, (short)0, (int)rec_bytes, 0x00020000);
+    if (tid == 0)
+        win[EKW_REC] = u32x4{0u, 0u, 0u, 0u};
+    uint32_t dp = 0, dn = 0;  // the lane's x, over every window of the run
     uint64_t ms = 0;
-    for (uint32_t j = 0; j < cmax; j += EKW_UNROLL) {
-        K2Batch<EKW_UNROLL> t;
-#pragma unroll
-        for (int u = 0; u < EKW_UNROLL; ++u) {
-            const uint32_t o = (uint32_t)fma(mf, rcp_up((double)(k0 + j + (uint32_t)u)), ny0);
-            t.off[u] = j + (uint32_t)u < cnt ? o : OFF_NONE;
+    for (uint32_t r = 0; r < EKW_RUN; ++r) {
+        const uint64_t Y0 = ystart + ((uint64_t)blockIdx.y * EKW_RUN + r) * EKW_Y;
+        if (Y0 >= yend || Y0 > b.y2)  // the same for the whole workgroup
+            break;
+        // the window's k: floor(m / (a 2^17)) = floor(floor(m / 2^17) / a)
+        uint64_t lo = 1, hi = 0;
+        if (act) {
+            const uint32_t a = (uint32_t)(Y0 >> EKW_SHIFT);  // < 2^14 (Y0 < 2^31)
+            const uint64_t kw_hi = div_small(mh, a), kw_lo = (uint64_t)div_small(mh, a + 1) + 1;
+            lo = klo_l > kw_lo ? klo_l : kw_lo;
+            hi = khi_l < kw_hi ? khi_l : kw_hi;
         }
+        const uint32_t cnt = lo <= hi ? (uint32_t)(hi - lo) + 1u : 0u;  // k < 2^31
+        const uint32_t cmax = (uint32_t)uniform_u64(wave_max_u64(cnt));
+        if (lane == 0)
+            wave_busy[r & 1u][wave] = cmax;
+        __syncthreads();  // the previous window's readers are done; flags written
+        uint32_t any = 0;
 #pragma unroll
-        for (int u = 0; u < EKW_UNROLL; ++u)
-            t.rec[u] = src(t.off[u]);
-        k2_consume<EKW_UNROLL>(t, dp, dn, ms);
+        for (uint32_t w = 0; w < EKW_TILES; ++w)
+            any |= wave_busy[r & 1u][w];
+        if (any == 0)  // no pair of the group in this window: skip its records
+            continue;
+        const uint32_t base = (uint32_t)((Y0 - b.y1) >> 5) * 16u;  // < 2^27
+        for (uint32_t i = tid; i < EKW_REC; i += EKW_THREADS)
+            win[i] = __builtin_amdgcn_raw_buffer_load_b128(rs, base + i * 16u, 0, 0);
+        __syncthreads();
+        // lane l walks the k of its x in this window (m 2^17 / Y0^2 of
+        // them: a few to thousands), reciprocals per pair
+        const double ny0 = -(double)Y0;
+        const uint32_t k0 = (uint32_t)lo;
+        for (uint32_t j = 0; j < cmax; j += EKW_UNROLL) {
+            K2Batch<EKW_UNROLL> t;
+#pragma unroll
+            for (int u = 0; u < EKW_UNROLL; ++u) {
+                const uint32_t o = (uint32_t)fma(mf, rcp_up((double)(k0 + j + (uint32_t)u)), ny0);
+                t.off[u] = j + (uint32_t)u < cnt ? o : OFF_NONE;
+            }
+#pragma unroll
+            for (int u = 0; u < EKW_UNROLL; ++u)
+                t.rec[u] = src(t.off[u]);
+            k2_consume<EKW_UNROLL>(t, dp, dn, ms);
+        }
     }
     const uint64_t mine = ms + (uint64_t)(int64_t)(int32_t)(dp - dn);
-    if (lane < nx && mine)
+    if (act && lane < nx && mine)
         atomicAdd((unsigned long long *)&q.S[g0 + lane], (unsigned long long)mine);
 }
 
@@ -2663,9 +2669,10 @@ hipError_t launch_ek_window(const QueryArgs &q, const BlockArgs &b, uint64_t yst
     // pass it for large batches)
     const uint32_t ngroups = (q.ntiles + EKW_TILES - 1) / EKW_TILES;
     const uint32_t nwin = (uint32_t)((yend - ystart + EKW_Y - 1) / EKW_Y);
-    if ((uint64_t)ngroups * EKW_THREADS >= (1ull << 32) || nwin >= (1u << 16))
+    const uint32_t nruns = (nwin + EKW_RUN - 1) / EKW_RUN;
+    if ((uint64_t)ngroups * EKW_THREADS >= (1ull << 32) || nruns >= (1u << 16))
         return hipErrorInvalidConfiguration;
-    hipLaunchKernelGGL(k_ek_window, dim3(ngroups, nwin), dim3(EKW_THREADS), 0, s, q, b, ystart,
+    hipLaunchKernelGGL(k_ek_window, dim3(ngroups, nruns), dim3(EKW_THREADS), 0, s, q, b, ystart,
                        yend);
     return hipGetLastError();
 }
