@@ -737,7 +737,11 @@ static_assert(SV_GPT == 4, "four 16-bit count fields per thread and segment");
 // the shift of o's byte within it.
 __device__ inline uint32_t sv_addr(uint32_t o)
 {
-    return (o & ~31u) | ((o & 7u) << 2);
+    // (o & ~31) | ((o & 7) << 2) as one bit-field insert of 4o into o (the
+    // compiler would spend two masks and an add on it)
+    uint32_t a;
+    __asm__("v_bfi_b32 %0, 31, %1, %2" : "=v"(a) : "v"(o << 2), "v"(o));
+    return a;
 }
 __device__ inline uint32_t sv_shift(uint32_t o)
 {
@@ -750,6 +754,35 @@ __device__ inline void sv_add(uint8_t *lb, uint32_t o, uint32_t v)
 __device__ inline void sv_square(uint8_t *lb, uint32_t o)
 {
     atomicOr(reinterpret_cast<uint32_t *>(lb + sv_addr(o)), 0x80u << sv_shift(o));
+}
+
+// The multiples o = f + p (lane + 64 i) < SEG of one prime (or square) p
+// taken by a whole wave (f, p wave-uniform; f < p).  A step of 64p keeps
+// each lane's byte and word within its 32-y group, so the word address
+// advances by 64p; the wave runs while lane 63's multiple (the largest) is
+// in the segment, a count kept in scalar registers, and then each lane
+// takes at most one more (its next multiple passes lane 63's last).
+template <bool SQUARE>
+__device__ inline void sv_wave_walk(uint8_t *lb, uint32_t f, uint32_t p, uint32_t lp,
+                                    uint32_t lane)
+{
+    const uint32_t o = f + __umul24(lane, p);
+    const uint32_t step = 64u * p;
+    const uint32_t v = (SQUARE ? 0x80u : lp) << sv_shift(o);
+    uint32_t a = sv_addr(o);
+    for (uint32_t o63 = f + 63u * p; o63 < SEG; o63 += step) {
+        if (SQUARE)
+            atomicOr(reinterpret_cast<uint32_t *>(lb + a), v);
+        else
+            atomicAdd(reinterpret_cast<uint32_t *>(lb + a), v);
+        a += step;
+    }
+    if (a < SEG) {
+        if (SQUARE)
+            atomicOr(reinterpret_cast<uint32_t *>(lb + a), v);
+        else
+            atomicAdd(reinterpret_cast<uint32_t *>(lb + a), v);
+    }
 }
 
 // mu masks of one 32-y group from its eight LDS words: pos (mu = +1) and
@@ -833,10 +866,12 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
     const uint32_t segbase0 = seg0 * SEG;  // < 2^31
 
     // ---- first multiple in each of the group's segments
-    // squares p^2, p <= SQ_LDS_P (index < n_sq_lds): wave w, lane j holds index w + 16 j
+    // squares p^2, p <= SQ_LDS_P (index < n_sq_lds): wave w, lane j holds
+    // index 15 - w + 16 j (the squares with many multiples go to the last
+    // waves, the small primes with many to the first)
     uint32_t q_p2 = 0, q_first[SV_R];
     {
-        const uint32_t i = wave + NWAVES * lane;
+        const uint32_t i = (NWAVES - 1u - wave) + NWAVES * lane;
         uint32_t f = 0, st = 0;
         if (i < b.n_sq_lds) {
             const uint32_t p = b.pres[i].x;
@@ -855,13 +890,14 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
     }
     // small primes (index in [FIRST_SIEVED, n_small)): wave w, lane j holds
     // index FIRST_SIEVED + w + 16 j
-    uint32_t s_p = 0, s_first[SV_R];
+    uint32_t s_p = 0, s_pl = 0, s_first[SV_R];
     {
         const uint32_t i = FIRST_SIEVED + wave + NWAVES * lane;
         uint32_t f = 0, st = 0;
         if (i < b.n_small) {
             const uint32_t p = b.pres[i].x;
             s_p = p;
+            s_pl = p | (log_prime(p) << 24);
             uint32_t r = b.pres[i].y + segbase0 % p;  // both < p < SMALL_P
             if (r >= p)
                 r -= p;
@@ -874,7 +910,11 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
             f = f >= st ? f - st : f + s_p - st;
         }
     }
-    const uint32_t nq_w = b.n_sq_lds > wave ? (b.n_sq_lds - wave + NWAVES - 1) / NWAVES : 0u;
+    // squares below SEG are walked by whole waves (the wave's first nq_w
+    // lanes hold them, in increasing order); larger ones (at most one
+    // multiple per segment) by their own lane
+    const uint32_t nq_w =
+        (uint32_t)__builtin_popcountll(__ballot(q_p2 != 0u && q_p2 < SEG));
     const uint32_t ns_w =
         b.n_small > FIRST_SIEVED + wave ? (b.n_small - FIRST_SIEVED - wave + NWAVES - 1) / NWAVES : 0u;
     // larger primes, one lane each: the first SV_U per thread carried
@@ -950,25 +990,18 @@ __global__ __launch_bounds__(SIEVE_THREADS) void k_sieve(BlockArgs b_in)
         }
         __syncthreads();
 
-        // squares p^2 <= SQ_LDS_P^2: one wave per prime, lane i takes multiple i
-        for (uint32_t jj = 0; jj < nq_w; ++jj) {
-            const uint32_t p2 = __builtin_amdgcn_readlane(q_p2, jj);
-            const uint32_t o = __builtin_amdgcn_readlane(q_first[j], jj) + __umul24(lane, p2);
-            if (o < SEG) {
-                const uint32_t v = 0x80u << sv_shift(o);
-                for (uint32_t a = sv_addr(o); a < SEG; a += 64 * p2)
-                    atomicOr(reinterpret_cast<uint32_t *>(lb + a), v);
-            }
-        }
+        // squares p^2 < SEG: one wave per prime, lane i takes multiples i, i+64, ...
+        for (uint32_t jj = 0; jj < nq_w; ++jj)
+            sv_wave_walk<true>(lb, __builtin_amdgcn_readlane(q_first[j], jj),
+                               __builtin_amdgcn_readlane(q_p2, jj), 0u, lane);
+        // squares SEG < p^2 <= SQ_LDS_P^2: one lane per prime
+        if (q_p2 > SEG && q_first[j] < SEG)
+            sv_square(lb, q_first[j]);
         // small primes: one wave per prime, lane i takes multiples i, i+64, ...
         for (uint32_t jj = 0; jj < ns_w; ++jj) {
-            const uint32_t p = __builtin_amdgcn_readlane(s_p, jj);
-            const uint32_t o = __builtin_amdgcn_readlane(s_first[j], jj) + __umul24(lane, p);
-            if (o < SEG) {
-                const uint32_t v = log_prime(p) << sv_shift(o);
-                for (uint32_t a = sv_addr(o); a < SEG; a += 64 * p)
-                    atomicAdd(reinterpret_cast<uint32_t *>(lb + a), v);
-            }
+            const uint32_t pl = __builtin_amdgcn_readlane(s_pl, jj);
+            sv_wave_walk<false>(lb, __builtin_amdgcn_readlane(s_first[j], jj), pl & 0xFFFFFFu,
+                                pl >> 24, lane);
         }
         // larger primes, carried: walk, then keep the offset in the next segment
 #pragma unroll
