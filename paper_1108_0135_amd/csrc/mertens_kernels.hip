@@ -1675,21 +1675,32 @@ __device__ inline double rcp_1ulp(double y)
     return fma(r, e, r);
 }
 
-// 1/k raised by four units in the last place (rcp_1ulp, then +4 in the
-// bits): for m < 2^48 the product m * rcp_up(k) rounded once lies in
-// [m/k, (m/k)(1 + 2^-49.5)], whose floor is floor(m/k) (see rl_pass).
+// 1/k raised by 2^-50 of itself: rcp_1ulp whose second Newton step aims at
+// (1 + 2^-50)/k.  With r1 = (1 - e1)/k after the first step (|e1| near
+// 2^-40), e = RN(1 + 2^-50 - k r1) = (2^-50 + e1)(1 + h) and
+// r' = RN(r1 + r1 e) = (1/k)(1 + 2^-50 - e1^2 - 2^-50 e1 + (2^-50 + e1) h
+// (1 - e1))(1 + h'), |h|, |h'| <= 2^-53: r' = (1/k)(1 + b) with b within
+// 2^-53 + 2^-79 of 2^-50, i.e. in [2^-50.2, 2^-49.8].  For m < 2^48 the
+// product m * rcp_up(k) rounded once then lies in [m/k, (m/k)(1 + 2^-49.6)],
+// whose floor is floor(m/k) (see rl_pass).
+constexpr double RCP_UP_ONE = 1.0000000000000008881784197001;  // 1 + 2^-50
+static_assert(RCP_UP_ONE == 1.0 + 0x1p-50, "1 + 2^-50 exactly");
 __device__ inline double rcp_up(double k)
 {
-    return __longlong_as_double(__double_as_longlong(rcp_1ulp(k)) + 4);
+    double r = __builtin_amdgcn_rcp(k);
+    double e = fma(-k, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-k, r, RCP_UP_ONE);
+    return fma(r, e, r);
 }
 
 // One pass of RL_XS x (m as fp64 in mf, NaN past the tile's end) over the
 // compacted entries.
-// * FAST (every m < 2^48, every y <= Y): with r within one ulp of 1/y
-//   (rcp_1ulp), r' = r raised by 4 ulps lies in [(1/y)(1 + 2^-52),
-//   (1/y)(1 + 2^-49.6)], so qd = RN(m r') lies in [m/y, (m/y)(1 + 2^-49.5)]:
-//   never below m/y, and above the next integer only if m/y were within
-//   (m/y) 2^-49.5 < 1/y of it, which m mod y >= 0 rules out.  floor(qd) =
+// * FAST (every m < 2^48, every y <= Y): r' = rcp_up(y) lies in
+//   [(1/y)(1 + 2^-50.2), (1/y)(1 + 2^-49.8)], so qd = RN(m r') lies in
+//   [m/y, (m/y)(1 + 2^-49.6)]: never below m/y, and above the next integer
+//   only if m/y were within (m/y) 2^-49.6 < 1/y of it, which m mod y >= 0
+//   rules out.  floor(qd) =
 //   floor(m/y) exactly: three fp64 ops per pair.
 // * otherwise: qh = m/y - 1/2 rounded once (fma); t = rint(qh) is
 //   floor(m/y) unless qh lies within QEPS of a half-integer, which the
@@ -1723,14 +1734,14 @@ __device__ inline void rl_pass(const uint16_t *ent, uint32_t total, uint32_t wb0
         const uint32_t y = wb0 + (e & 0x0FFFu);
         const double sg = (e & 0x8000u) ? -1.0 : 1.0;
         if (MODE == RL_FAST) {
-            const double ru = __longlong_as_double(__double_as_longlong(rcp_1ulp((double)y)) + 4);
+            const double ru = rcp_up((double)y);
 #pragma unroll
             for (int i = 0; i < RL_XS; ++i)
                 acc[i] = fma(sg, floor(mf[i] * ru), acc[i]);
             continue;
         }
         if (MODE == RL_FAST23) {
-            const double ru = __longlong_as_double(__double_as_longlong(rcp_1ulp((double)y)) + 4);
+            const double ru = rcp_up((double)y);
             int si = (e & 0x8000u) ? -1 : 1;
             // opaque: a known +-1 factor is otherwise expanded into a
             // conditional negation (four ops instead of one multiply-add)
@@ -2207,15 +2218,12 @@ struct RecGlobal {
         return __builtin_amdgcn_raw_buffer_load_b128(rs, (off >> 1) & ~15u, 0, 0);
     }
 };
-// LDS: a window of nrec records followed by one empty record.
+// LDS: a window of EKW_REC records followed by one empty record.  Offsets
+// are below 32 EKW_REC (a pair's quotient lies in the window) or equal to
+// EKW_NONE, which names the empty record.
 struct RecLds {
     const u32x4 *win;
-    uint32_t nrec;
-    __device__ u32x4 operator()(uint32_t off) const
-    {
-        const uint32_t r = off >> 5;
-        return win[r < nrec ? r : nrec];
-    }
+    __device__ u32x4 operator()(uint32_t off) const { return win[off >> 5]; }
 };
 
 // One batch of the walk: U pairs per lane, k = sb + i0 + 8u.
@@ -2287,7 +2295,7 @@ __device__ inline void k2_walk(const Src &src, const double *rk, uint64_t sb, ui
 // * y - y1 = trunc(fma(m, rcp_up(k), -y1)).  In a block from y1 = 0 this is
 //   the product above.  From y1 > 0 with y2 - y1 < y1: active pairs have
 //   k <= m/y1, so the product's excess over floor(m/k) stays below the next
-//   integer by more than (1/k)(1 - m 2^-49.6) >= 0.67 y1/m, while the one
+//   integer by more than (1/k)(1 - m 2^-49.8) >= 0.67 y1/m, while the one
 //   rounding of the fused result (< 2^31 = y2 - y1 + 1 <= y1) moves it by at
 //   most (y2 - y1 + 1) 2^-53 < 0.67 y1 / m; rounding never goes below the
 //   integer floor(m/k) - y1 either, since the exact value exceeds it.
@@ -2590,6 +2598,7 @@ hipError_t launch_update(const QueryArgs &q, const BlockArgs &b, uint32_t grid, 
 // yend <= 2^31.
 constexpr uint32_t EKW_Y = 1u << EKW_SHIFT;
 constexpr uint32_t EKW_REC = EKW_Y / 32;  // 4096 records = 64 KiB
+constexpr uint32_t EKW_NONE = EKW_REC * 32;  // offset of the empty record after them
 constexpr int EKW_THREADS = 1024;
 constexpr uint32_t EKW_TILES = EKW_THREADS / 64;
 constexpr int EKW_UNROLL = 4;  // LDS reads per lane and batch (eight spill at 64 VGPRs)
@@ -2637,7 +2646,7 @@ __global__ __launch_bounds__(EKW_THREADS, 8) void k_ek_window(QueryArgs q, Block
     }
     const uint32_t mh = act ? (uint32_t)(m_l >> EKW_SHIFT) : 0u;  // m < 2^48: < 2^31
     const double mf = (double)m_l;
-    const RecLds src{win, EKW_REC};
+    const RecLds src{win};
     const uint32_t rec_bytes = ((uint32_t)((b.y2 - b.y1) >> 5) + 1u) * 16u;
     const __amdgpu_buffer_rsrc_t rs =
         __builtin_amdgcn_make_buffer_rsrc(b.words, (short)0, (int)rec_bytes, 0x00020000);
@@ -2675,13 +2684,13 @@ __global__ __launch_bounds__(EKW_THREADS, 8) void k_ek_window(QueryArgs q, Block
         // lane l walks the k of its x in this window (m 2^17 / Y0^2 of
         // them: a few to thousands), reciprocals per pair
         const double ny0 = -(double)Y0;
-        const uint32_t k0 = (uint32_t)lo;
-        for (uint32_t j = 0; j < cmax; j += EKW_UNROLL) {
+        double kd = (double)lo;  // k of the batch's first pair (exact: k < 2^32)
+        for (uint32_t j = 0; j < cmax; j += EKW_UNROLL, kd += (double)EKW_UNROLL) {
             K2Batch<EKW_UNROLL> t;
 #pragma unroll
             for (int u = 0; u < EKW_UNROLL; ++u) {
-                const uint32_t o = (uint32_t)fma(mf, rcp_up((double)(k0 + j + (uint32_t)u)), ny0);
-                t.off[u] = j + (uint32_t)u < cnt ? o : OFF_NONE;
+                const uint32_t o = (uint32_t)fma(mf, rcp_up(kd + (double)u), ny0);
+                t.off[u] = j + (uint32_t)u < cnt ? o : EKW_NONE;
             }
 #pragma unroll
             for (int u = 0; u < EKW_UNROLL; ++u)

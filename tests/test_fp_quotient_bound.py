@@ -1,16 +1,19 @@
 """The fp64 quotient rule of the run-length update, checked on the CPU.
 
 For m < 2^48 and 1 <= y < 2^32, the device takes floor(m/y) as
-floor(RN(m * r')) with r' a reciprocal r of y within one unit in the last
-place (a hardware estimate refined by two Newton steps) raised by four
-units in the last place (no remainder test).  The rule is checked here with
-r = RN(1/y) and with r one unit below and above it (a wider error than the
-device's): IEEE binary64 multiply and divide are correctly rounded on the
-CPU as on the GPU, so numpy reproduces the rule's values bit for bit.  It
-must hold on random pairs and on the adversarial ones: exact multiples
-(m = k y), m = k y - 1 just below them, and the largest m allowed.
+floor(RN(m * r')) with r' = (1/y)(1 + b), b in [2^-50.2, 2^-49.8]: a
+hardware estimate refined by one Newton step, then a second step aimed at
+(1 + 2^-50)/y (no remainder test).  The construction of r' is checked in
+exact rational arithmetic (test_biased_newton_step); the rule is checked
+with r' = RN(1/y) raised by three, four and five units in the last place,
+biases of 2^-51.4 ... 2^-49.7 that cover b's range.  IEEE binary64 multiply
+and divide are correctly rounded on the CPU as on the GPU, so numpy
+reproduces the rule's values bit for bit.  It must hold on random pairs and
+on the adversarial ones: exact multiples (m = k y), m = k y - 1 just below
+them, and the largest m allowed.
 """
 from fractions import Fraction
+import math
 
 import numpy as np
 
@@ -152,4 +155,77 @@ def test_magic_low_word():
             for e in (-1, 0, 1):
                 if _magic_quot(mm, y, e) != mm // y:
                     bad.append((mm, y, e))
+    assert not bad, bad[:5]
+
+
+# The reciprocal itself: r1 = (1 - e1)/k after the first Newton step (the
+# hardware estimate's error squared, near 2^-40 or far below), then
+# e = RN(1 + 2^-50 - k r1) (one fused rounding) and r' = RN(r1 + r1 e).
+
+def _biased_newton(k, r1):
+    one_c = Fraction(1) + Fraction(1, 2**50)
+    assert float(one_c) == 1.0 + 2.0**-50  # exactly representable
+    e = float(one_c - k * Fraction(r1))
+    return float(Fraction(r1) + Fraction(r1) * Fraction(e))
+
+
+def _bias_log2(k, r):
+    b = Fraction(r) * k - 1
+    assert b > 0
+    return math.log2(b)
+
+
+def test_biased_newton_step():
+    rng = np.random.default_rng(15)
+    ks = [1, 2, 3, 5, 7, 2**20 - 1, 2**20, 2**20 + 1, 2**31 - 1, 2**31, 2**32 - 1,
+          2**32 - 5, 3 * 2**29, 1431655765]
+    ks += [int(v) for v in rng.integers(1, 2**32, 3000)]
+    lo, hi = 0.0, -100.0
+    for k in ks:
+        rn = 1.0 / k
+        base = [rn, float(np.nextafter(rn, 0.0)), float(np.nextafter(rn, 1.0))]
+        for eps in (2.0**-40, -2.0**-40, 2.0**-45, -2.0**-45):
+            base.append(float(Fraction(1, k) * (1 + Fraction(eps))))
+        for r1 in base:
+            t = _bias_log2(k, _biased_newton(k, r1))
+            assert -50.2 <= t <= -49.8, (k, r1, t)
+            lo, hi = min(lo, t), max(hi, t)
+    assert lo < -50.1 and hi > -49.9  # both ends of the range are reached
+
+
+def test_biased_reciprocal_floors():
+    # the floor rules with r' built as on the device (r1 = RN(1/k) and one
+    # unit off), on the adversarial m of each kind
+    rng = np.random.default_rng(16)
+    bad = []
+    for _ in range(1500):
+        k = int(rng.integers(1, 2**32))
+        rn = 1.0 / k
+        for r1 in (rn, float(np.nextafter(rn, 0.0)), float(np.nextafter(rn, 1.0))):
+            ru = _biased_newton(k, r1)
+            num, den = Fraction(ru).as_integer_ratio()
+            qmax = (2**48 - 1) // k
+            if qmax < 1:
+                continue
+            q = int(rng.integers(1, qmax + 1))
+            for m in (q * k, q * k + k - 1, q * k - 1):
+                if not 0 < m < 2**48:
+                    continue
+                # plain product: floor(RN(m r'))
+                if math.floor(float(Fraction(m * num, den))) != m // k:
+                    bad.append(("plain", m, k, r1))
+                # the magic-constant low word, for quotients below 2^23
+                if m // k < 2**23:
+                    v = float(Fraction(2 * m * num + (2**53 - 1) * den, 2 * den))
+                    low = int(np.array([v]).view(np.int64)[0]) - \
+                        int(np.array([2.0**52]).view(np.int64)[0])
+                    if low != m // k:
+                        bad.append(("magic", m, k, r1))
+                # the fused block offset, for a block [y1, y2] holding q with
+                # y2 - y1 < y1
+                y1 = (m // k) // 2 + 1 if m // k >= 2 else 0
+                if y1 == 0 or m // k - y1 < y1:
+                    off = int(float(Fraction(m * num - y1 * den, den)))
+                    if off != m // k - y1:
+                        bad.append(("fused", m, k, r1, y1))
     assert not bad, bad[:5]
