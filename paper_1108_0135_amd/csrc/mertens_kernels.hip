@@ -2248,14 +2248,23 @@ __device__ inline void k2_issue(K2Batch<U> &t, const Src &src, const double *rk,
         t.rec[u] = src(t.off[u]);
 }
 
+// acc + popcount(x) in one op (the compiler counts into zero and adds the
+// counts with three-input adds: one op more per pair)
+__device__ inline uint32_t popc_add(uint32_t x, uint32_t acc)
+{
+    uint32_t r;
+    __asm__("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+    return r;
+}
+
 template <int U>
 __device__ inline void k2_consume(const K2Batch<U> &t, uint32_t &dp, uint32_t &dn, uint64_t &ms)
 {
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const uint32_t sh = ~t.off[u] & 31u;
-        dp += (uint32_t)__popc(t.rec[u].x << sh);
-        dn += (uint32_t)__popc(t.rec[u].y << sh);
+        dp = popc_add(t.rec[u].x << sh, dp);
+        dn = popc_add(t.rec[u].y << sh, dn);
         ms += (uint64_t)t.rec[u].z | ((uint64_t)t.rec[u].w << 32);
     }
 }
