@@ -194,7 +194,10 @@ int mertens_set_stream(void *hip_stream);
  *                 blocks)
  *   "bucket_min"  a block sieving at least this many primes above 2^17
  *                 lists their multiples in per-segment buckets first
- *                 (default 2^20; scanning them per segment is faster below)
+ *                 (default 2^20; scanning them per segment is faster below);
+ *                 a block also buckets them when they outnumber the
+ *                 multiples they leave in a 2^17-y segment eight times or
+ *                 more (from y near 1.5e13 on)
  *   "rl_fast"     1 (default): run-length quotients with m < 2^48 take the
  *                 test-free rounded-up fp64 floor, and explicit-k quotients
  *                 of such x the test-free fused form; 0: always the tested
@@ -282,7 +285,8 @@ const char *mertens_last_error(void);
  * The sweep sieves mu over [a - (a mod 2^17), b] in blocks (the init block
  * size, or automatically up to 2^31 y; device primes up to ceil(sqrt(b)),
  * those above 2^17 through per-segment buckets once there are "bucket_min"
- * of them), runs the M(y) prefix from zero, and shifts it by M(a) minus the
+ * of them or eight per multiple in a segment), runs the M(y) prefix from
+ * zero, and shifts it by M(a) minus the
  * prefix at a.
  * mertens_stats afterwards: sieved_y, blocks, ms_sieve (the sieve kernel
  * with its fused prefix), ms_prep (block set-up, square and prime buckets),

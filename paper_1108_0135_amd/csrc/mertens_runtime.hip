@@ -404,7 +404,7 @@ struct SieveState {
         // bucketed primes: counts, starts, and every multiple in a block of
         // any prime above SEG (at most B / p + 1 each)
         const uint32_t n_mid = count_primes_upto(SEG);
-        if (h_primes.size() - n_mid >= bucket_min) {
+        if (bucketed(h_primes.size(), psieve)) {
             if (bk_cap_B != B || bk_cap_np != h_primes.size()) {
                 long double c = 0;
                 for (size_t i = n_mid; i < h_primes.size(); ++i)
@@ -430,6 +430,26 @@ struct SieveState {
         return 0;
     }
 
+    // Whether a block whose n_sieve sieving primes reach pmax lists the
+    // multiples of its primes above SEG in buckets: when there are
+    // bucket_min of them, or when they outnumber the multiples they leave in
+    // a segment (SEG times the sum of 1/p over (SEG, pmax], by Mertens'
+    // second theorem about SEG ln(ln pmax / ln SEG)) BK_RATIO times or more:
+    // without buckets each such prime costs a residue in every segment,
+    // with them each multiple costs a listed entry.
+    static constexpr double BK_RATIO = 8.0;
+    bool bucketed(uint64_t n_sieve, uint64_t pmax) const
+    {
+        const uint64_t n_mid = count_primes_upto(SEG);
+        if (n_sieve <= n_mid)
+            return false;
+        const uint64_t n_above = n_sieve - n_mid;
+        if (n_above >= bucket_min)
+            return true;
+        const double hits = (double)SEG * std::log(std::log((double)pmax) / std::log((double)SEG));
+        return (double)n_above >= BK_RATIO * hits;
+    }
+
     uint32_t count_primes_upto(uint64_t v) const  // # table primes p <= v
     {
         return (uint32_t)(std::upper_bound(h_primes.begin(), h_primes.end(), v,
@@ -448,7 +468,8 @@ struct SieveState {
         // primes up to sqrt(y2) decide mu on the block (and every p < SMALL_P)
         b.n_sieve = count_primes_upto(std::max<uint64_t>(ceil_sqrt_host(y2), SMALL_P));
         const uint32_t n_mid = count_primes_upto(SEG);
-        b.n_bucket = (b.n_sieve > n_mid && b.n_sieve - n_mid >= bucket_min) ? n_mid : b.n_sieve;
+        b.n_bucket = bucketed(b.n_sieve, std::max<uint64_t>(ceil_sqrt_host(y2), SMALL_P)) ? n_mid
+                                                                                        : b.n_sieve;
         b.n_lane = std::max(b.n_bucket, count_primes_upto((uint64_t)b.nseg * SEG / 64));
         b.n_lane = std::min(b.n_lane, b.n_sieve);
         b.bk_cnt = bk_cnt.as<uint32_t>();
@@ -516,7 +537,7 @@ struct SieveState {
         b.n_sieve = (uint32_t)h_primes.size();
         // capture the bucket kernels whenever some block may use them
         const uint32_t n_mid = count_primes_upto(SEG);
-        b.n_bucket = (b.n_sieve > n_mid && b.n_sieve - n_mid >= bucket_min) ? n_mid : b.n_sieve;
+        b.n_bucket = bucketed(b.n_sieve, psieve) ? n_mid : b.n_sieve;
         b.n_lane = std::min(std::max(b.n_bucket, count_primes_upto(B / 64)), b.n_sieve);
         return b;
     }
