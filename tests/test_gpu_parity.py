@@ -477,7 +477,7 @@ def test_table1_1e20_and_byproducts(mt):
 
 
 @pytest.mark.skipif(os.environ.get("MERTENS_LONG") != "1",
-                    reason="about 10 minutes on one MI355X; set MERTENS_LONG=1 to run")
+                    reason="about 8 minutes on one MI355X; set MERTENS_LONG=1 to run")
 def test_table1_1e21_magnitude_and_byproducts(mt):
     # Table 1 prints M(10^21) = 3395895277; the library computes
     # -3395895277.  Only the magnitude and the byproducts M(10^20),
